@@ -1,0 +1,202 @@
+/*
+ * clgen.h -- C ABI of the MI355X (gfx950) Chung-Lu edge generator.
+ *
+ * Problem (Alam & Khan, "Parallel Algorithms for Generating Random Networks
+ * with Given Degree Sequences", Sec. 3): given n non-negative weights
+ * w_0 >= w_1 >= ... >= w_{n-1} and S = sum_k w_k, produce a random graph in
+ * which every pair {u,v} is an edge independently with probability
+ * min(w_u w_v / S, 1).  The generator is Create-Edges(w, S, V) of Alg. 1
+ * (geometric skipping): S and the source range V are explicit inputs.
+ *
+ * Conventions for every call:
+ *   - pointers are device pointers unless the comment says "host";
+ *   - `stream` is a hipStream_t (NULL = the null stream); work is enqueued on
+ *     it; calls documented as "synchronises" wait for their own work;
+ *   - the caller owns every buffer (weights, workspace, edges); the library
+ *     never allocates device memory and keeps no state between calls;
+ *   - errors are returned as negative cl_status values, never thrown.
+ *
+ * Output of the generator: uint32 pairs (u, v) with u < v, sorted by (u, v),
+ * node ids being positions in the sorted weight vector.  The edge list is a
+ * pure function of (w, S, seed, range): it does not depend on the launch
+ * schedule, the lane budget or the number of graphs in a batch.
+ *
+ * Sampling rule (the points Alg. 1 leaves open, fixed so that any conforming
+ * implementation gives the same bits):
+ *   - random words: Philox4x32-10 with counter (t, k, u, 0) and key
+ *     (seed mod 2^32, seed >> 32); t counts the draws of segment k of source u;
+ *   - uniforms r_skip = U53(x1:x0), r_acc = U53(x3:x2), U53(x) = (2(x>>12)+1) 2^-53;
+ *   - p = min((w_u / S) w_v, 1); skip delta = floor(LN(r_skip) / LN1M(p)) with
+ *     binary64 logs built from a fixed range reduction and an 11-term atanh
+ *     series; the segment ends when the skip leaves it; keep v iff r_acc p < q;
+ *   - sources whose expected edge count e_u (Eq. 1 on the quantised prefix
+ *     q_v = floor(w_v 2^32 / w_0)) exceeds 256 are split into
+ *     min(ceil(e_u / 256), n-u-1) segments of equal quantised mass.
+ */
+#ifndef CLGEN_H_
+#define CLGEN_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cl_status;
+
+#define CL_OK               0
+#define CL_ERR_INVALID_ARG (-1)  /* bad pointer/size/range, S <= 0, S < w_0, 0 < w_0 < 2^-960 */
+#define CL_ERR_UNSORTED    (-2)  /* weights not non-increasing (Sec. 3 input condition) */
+#define CL_ERR_NEGATIVE    (-3)  /* a negative weight */
+#define CL_ERR_NONFINITE   (-4)  /* a NaN or infinite weight (or an infinite sum) */
+#define CL_ERR_TOO_LARGE   (-5)  /* n >= 2^32 (node ids are uint32) */
+#define CL_ERR_WORKSPACE   (-6)  /* workspace too small; the required size is reported */
+#define CL_ERR_CAPACITY    (-7)  /* a size exceeded what the workspace was laid out for */
+#define CL_ERR_DEVICE      (-8)  /* a HIP runtime error */
+#define CL_ERR_NOT_PLANNED (-9)  /* workspace does not hold a plan from cl_count */
+
+/* One generation task: Create-Edges(w, S, [u_begin, u_end)) of Alg. 1. */
+typedef struct cl_graph {
+  const double* w;     /* device, n weights, non-increasing, finite, >= 0 */
+  uint64_t n;          /* < 2^32 */
+  double S;            /* > 0, >= w[0]; normally the exact sum (cl_weight_sum) */
+  uint64_t seed;       /* Philox key */
+  uint64_t u_begin;    /* source range, 0 <= u_begin <= u_end <= n */
+  uint64_t u_end;
+} cl_graph;
+
+/* Schedule knobs.  They change the launch schedule only, never an output bit.
+ * Zero fields take the defaults. */
+typedef struct cl_tuning {
+  uint32_t lane_budget;    /* expected candidates per lane (Eq. 5 chunk size), default 192 */
+  uint32_t blocks_per_cu;  /* persistent grid = compute units x this, default 8 */
+  uint32_t reserved0;
+  uint32_t reserved1;
+} cl_tuning;
+
+/* ---------------------------------------------------------------------------
+ * S <- sum_k w_k (Alg. 1, first line; Sec. 4 "parallel sum").  Returns the
+ * exactly rounded sum (the real sum rounded once to nearest-even), which does
+ * not depend on the summation order.  Also validates w (sorted, >= 0, finite).
+ * ws: device workspace of cl_weight_sum_workspace() bytes.  S_out: host.
+ * Synchronises.
+ * ------------------------------------------------------------------------- */
+cl_status cl_weight_sum_workspace(uint64_t n, uint64_t* bytes_out /* host */);
+cl_status cl_weight_sum(const double* w, uint64_t n, void* ws, uint64_t ws_bytes,
+                        double* S_out /* host */, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * E[m] = sum_{u<v} min(w_u w_v / S, 1) (Eq. 1 with the cap; m = sum_u e_u of
+ * Sec. 4) and Var[m] = sum_{u<v} p (1 - p), p as used by the sampler.  Float64,
+ * sorted closed form (capped candidates of u form a prefix of v > u).
+ * Em_out, Var_out: host.  Synchronises.
+ * ------------------------------------------------------------------------- */
+cl_status cl_expected_edges_workspace(uint64_t n, uint64_t* bytes_out /* host */);
+cl_status cl_expected_edges(const double* w, uint64_t n, double S, void* ws, uint64_t ws_bytes,
+                            double* Em_out /* host */, double* Var_out /* host */, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Uniform consecutive partition (Sec. 4, Eq. 2, Eq. 5, Alg. 2): bounds
+ * n_0 = 0 <= n_1 <= ... <= n_P = n with n_k = min{u : C_u >= k Z / P}, where
+ * C_u is the cumulative cost of sources 0..u, c_u = e_u + 1 (Eq. 2) with e_u
+ * from Eq. 6 on the quantised prefix, kept in units of 1/256 (c_u =
+ * floor(256 e_u) + 256) so that C_u is an exact integer, and Z = C_{n-1}.
+ * Partition i is [n_i, n_{i+1}); partitions may be empty.
+ * bounds_out: host, P + 1 entries.  Synchronises.
+ * ------------------------------------------------------------------------- */
+cl_status cl_partition_workspace(uint64_t n, uint32_t P, uint64_t* bytes_out /* host */);
+cl_status cl_partition(const double* w, uint64_t n, double S, uint32_t P, void* ws, uint64_t ws_bytes,
+                       uint64_t* bounds_out /* host */, uint64_t* total_cost_out /* host, may be NULL */,
+                       void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Generation, count pass (Alg. 1 run once to count).  Plans G independent
+ * tasks in one workspace: validation, the quantised prefix, per-source costs
+ * (Eq. 1-2) and segments, the lane plan (Eq. 5 applied to lanes), then counts
+ * the edges of every lane and forms their output offsets.
+ * m_out: host, G entries (edges per task).  ws_required (host, may be NULL)
+ * receives the bytes the workspace needs; when ws_bytes is smaller the call
+ * returns CL_ERR_WORKSPACE without generating (call again with a larger ws).
+ * cl_workspace_size gives the size of the part known before the data is seen
+ * (fixed_bytes) and an estimate of the whole (estimate_bytes).
+ * Synchronises twice (sizes, counts).
+ * ------------------------------------------------------------------------- */
+cl_status cl_workspace_size(const cl_graph* g /* host, G entries */, uint32_t G, const cl_tuning* t,
+                            uint64_t* fixed_bytes /* host */, uint64_t* estimate_bytes /* host */);
+cl_status cl_count(const cl_graph* g /* host, G entries */, uint32_t G, const cl_tuning* t,
+                   void* ws, uint64_t ws_bytes, uint64_t* m_out /* host */,
+                   uint64_t* ws_required /* host, may be NULL */, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Generation, write pass: replays the planned lanes with the same random
+ * words and writes every edge whose position in the batch output lies in
+ * [edge_begin, edge_begin + cap) to edges[2 (pos - edge_begin) + {0,1}] as
+ * (u, v).  Task g's edges occupy positions [off_g, off_g + m_g), off_g = sum of
+ * m_h for h < g.  graph_offsets (device, G + 1 entries, may be NULL) receives
+ * off_0..off_{G-1} and the total.  Writing the output in windows (slabs)
+ * costs each window only the lanes that overlap it.  Asynchronous.
+ * ws must hold the plan of a successful cl_count (same inputs, unchanged).
+ * ------------------------------------------------------------------------- */
+cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t edge_begin, uint64_t cap,
+                      uint64_t* graph_offsets, void* stream);
+
+/* Totals of the plan in ws (host outputs; synchronises).  lanes includes the
+ * padding to whole wavefronts. */
+cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments, uint64_t* edges,
+                       void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Digest of an edge list: acc += sum_i mix(mix(index_base + i) ^ (u_i 2^32 + v_i))
+ * mod 2^64, mix = splitmix64's output function.  Order independent
+ * reduction, position keyed.  acc: device uint64 the caller initialises.
+ * Asynchronous.
+ * ------------------------------------------------------------------------- */
+cl_status cl_hash_edges(const uint32_t* edges, uint64_t m, uint64_t index_base, uint64_t* acc, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched generation as one replayable HIP graph: records the whole path
+ * (validation, prefix, plan, count, offsets, write) for the G tasks planned in
+ * ws by a preceding cl_count (same g), with the sizes of that plan, on a
+ * non-null stream in capture mode.  Each replay regenerates all G edge lists
+ * into edges[0 .. 2 cap) with no host synchronisation; graph_offsets (device,
+ * G + 1) receives the task offsets.  If a replay finds larger sizes than the
+ * plan (changed inputs) it writes nothing and cl_plan_info reports 0 edges.
+ * ------------------------------------------------------------------------- */
+cl_status cl_batch_capture(const cl_graph* g /* host */, uint32_t G, const cl_tuning* t, void* ws,
+                           uint32_t* edges, uint64_t cap, uint64_t* graph_offsets,
+                           void** graph_exec_out /* host */, void* stream);
+cl_status cl_batch_launch(void* graph_exec, void* stream);
+cl_status cl_batch_destroy(void* graph_exec);
+
+/* ---------------------------------------------------------------------------
+ * Expected degrees under the capped model (Sec. 3, with j != i and the cap):
+ *   d_i = sum_{j != i} min(w_i w_j / S, 1).
+ * w: float32 (any order).  Pair terms in float32, accumulated in float32 over
+ * tiles of columns; tile partials summed in float64.  d_out: float64.
+ * ws: cl_expected_degree_workspace bytes.  Asynchronous.
+ * ------------------------------------------------------------------------- */
+cl_status cl_expected_degree_workspace(uint64_t n, uint64_t* bytes_out /* host */);
+cl_status cl_expected_degree(const float* w, uint64_t n, double S, double* d_out, void* ws, uint64_t ws_bytes,
+                             void* stream);
+
+/* Adjoint of cl_expected_degree: given g = dL/dd (float64), writes
+ *   grad_w[k] = (g_k A_k + B_k - T) / S,  A_k = sum_{j != k, x_kj < 1} w_j,
+ *   B_k = sum_{j != k, x_kj < 1} g_j w_j,  T = sum_i g_i sum_{j != i, x_ij < 1} x_ij,
+ * x_ij = w_i w_j / S; the T term (dS/dw_k = 1) only when s_depends_on_w != 0.
+ * Pairs with x_ij >= 1 are capped (zero derivative).  grad_w: float32.
+ * Asynchronous. */
+cl_status cl_expected_degree_backward(const float* w, uint64_t n, double S, const double* grad_d,
+                                      int s_depends_on_w, float* grad_w, void* ws, uint64_t ws_bytes,
+                                      void* stream);
+
+/* Number of compute units of the current device (host; 0 on error). */
+uint32_t cl_device_cus(void);
+
+/* Version string of the library (host, static storage). */
+const char* cl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLGEN_H_ */

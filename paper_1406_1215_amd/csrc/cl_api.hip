@@ -1,0 +1,608 @@
+// C ABI of the generator (declarations and contracts in include/clgen.h).
+// Host side only: argument checks, workspace layout, launches.  Every step of
+// the computation runs in the kernels of cl_kernels.hpp, cl_stats.hpp and
+// cl_expdeg.hpp.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "clgen.h"
+#include "cl_expdeg.hpp"
+#include "cl_kernels.hpp"
+#include "cl_plan.hpp"
+#include "cl_scan.hpp"
+#include "cl_stats.hpp"
+
+using namespace cl;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr uint32_t kDefaultBudget = 192;
+constexpr uint32_t kDefaultBlocksPerCu = 8;
+constexpr int kPersistThreads = 256;
+
+inline uint64_t align_up(uint64_t x, uint64_t a = kAlign) { return (x + a - 1) / a * a; }
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline cl_status hip_status(hipError_t e) { return e == hipSuccess ? CL_OK : CL_ERR_DEVICE; }
+
+#define CL_TRY(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return CL_ERR_DEVICE;        \
+  } while (0)
+
+uint32_t cus_of_current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return static_cast<uint32_t>(cus);
+}
+
+cl_status status_error(uint32_t st) {
+  if (st & kStNonfinite) return CL_ERR_NONFINITE;
+  if (st & kStNegative) return CL_ERR_NEGATIVE;
+  if (st & kStUnsorted) return CL_ERR_UNSORTED;
+  if (st & kStBadS) return CL_ERR_INVALID_ARG;
+  if (st & kStCapacity) return CL_ERR_CAPACITY;
+  if (st & kStCostOverflow) return CL_ERR_TOO_LARGE;
+  return st ? CL_ERR_DEVICE : CL_OK;
+}
+
+uint32_t grid_for(uint64_t items, uint32_t threads, uint32_t cap_blocks) {
+  uint64_t b = (items + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > cap_blocks) b = cap_blocks;
+  return static_cast<uint32_t>(b);
+}
+
+uint32_t stream_grid_cap() {
+  const uint32_t cus = cus_of_current_device();
+  return std::max<uint32_t>(cus, 1) * 16;
+}
+
+bool finite_pos(double x) { return x > 0.0 && x <= 1.7976931348623157e308; }
+
+// ---------------------------------------------------------------- layouts
+struct FixedLayout {
+  uint64_t off_desc, off_Q, off_C, off_SB, off_scan, off_m, bytes;
+  uint64_t total_q, total_r, scan_elems;
+};
+
+FixedLayout fixed_layout(const cl_graph* g, uint32_t G) {
+  FixedLayout L{};
+  uint64_t tq = 0, tr = 0;
+  for (uint32_t i = 0; i < G; ++i) {
+    tq += g[i].n + 1;
+    tr += (g[i].u_end - g[i].u_begin) + 1;
+  }
+  L.total_q = tq;
+  L.total_r = tr;
+  // scan partials: Triple tiles of the source scan or u64 tiles of the Q scan
+  L.scan_elems = std::max<uint64_t>(scan_tiles(tq), 3 * scan_tiles(tr)) + 8;
+  uint64_t off = align_up(sizeof(WsHeader));
+  L.off_desc = off;
+  off = align_up(off + sizeof(GraphDesc) * G);
+  L.off_Q = off;
+  off = align_up(off + 8 * tq);
+  L.off_C = off;
+  off = align_up(off + 8 * tr);
+  L.off_SB = off;
+  off = align_up(off + 8 * tr);
+  L.off_scan = off;
+  off = align_up(off + 8 * L.scan_elems);
+  L.off_m = off;
+  off = align_up(off + 8 * G);
+  L.bytes = off;
+  return L;
+}
+
+struct VarLayout {
+  uint64_t off_hseg, off_lstart, off_lcnt, off_lpos, off_lscan, off_groups, bytes;
+};
+
+VarLayout var_layout(uint64_t base, uint64_t nh, uint64_t nl) {
+  VarLayout V{};
+  uint64_t off = align_up(base);
+  V.off_hseg = off;
+  off = align_up(off + 4 * std::max<uint64_t>(nh, 1));
+  V.off_lstart = off;
+  off = align_up(off + 8 * std::max<uint64_t>(nl, 1));
+  V.off_lcnt = off;
+  off = align_up(off + 4 * std::max<uint64_t>(nl, 1));
+  V.off_lpos = off;
+  off = align_up(off + 8 * (nl + 1));
+  V.off_lscan = off;
+  off = align_up(off + 8 * (scan_tiles(nl + 1) + 8));
+  V.off_groups = off;
+  off = align_up(off + 4 * std::max<uint64_t>(nl / kLaneGroup, 1));
+  V.bytes = off;
+  return V;
+}
+
+cl_status check_graphs(const cl_graph* g, uint32_t G) {
+  if (!g || G == 0) return CL_ERR_INVALID_ARG;
+  for (uint32_t i = 0; i < G; ++i) {
+    if (g[i].n >= 4294967296ull) return CL_ERR_TOO_LARGE;
+    if (g[i].n > 0 && g[i].w == nullptr) return CL_ERR_INVALID_ARG;
+    if (!finite_pos(g[i].S)) return CL_ERR_INVALID_ARG;
+    if (g[i].u_begin > g[i].u_end || g[i].u_end > g[i].n) return CL_ERR_INVALID_ARG;
+  }
+  return CL_OK;
+}
+
+uint64_t budget_units(const cl_tuning* t) {
+  const uint32_t b = (t && t->lane_budget) ? t->lane_budget : kDefaultBudget;
+  return static_cast<uint64_t>(b) * kCostUnit;
+}
+
+uint32_t persistent_grid(const cl_tuning* t) {
+  const uint32_t bpc = (t && t->blocks_per_cu) ? t->blocks_per_cu : kDefaultBlocksPerCu;
+  return std::max<uint32_t>(cus_of_current_device(), 1) * bpc;
+}
+
+// the phase of the plan that needs no sizes from the device: validation,
+// quantised prefix, per-source prefixes, per-graph sizes
+hipError_t launch_plan_front(WsHeader* dhdr, const WsHeader& h, uint32_t G, hipStream_t s) {
+  const uint32_t cap = stream_grid_cap();
+  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(256), 0, s, dhdr);
+  hipLaunchKernelGGL(k_graph_init, dim3((G + 255) / 256), dim3(256), 0, s, h.desc, G);
+  hipLaunchKernelGGL((k_validate<false>), dim3(grid_for(h.total_q, 256, cap)), dim3(256), 0, s, h.desc, G,
+                     h.total_q, static_cast<unsigned long long*>(nullptr));
+  hipError_t e = device_scan<uint64_t>(QIn{h.desc, G}, QOut{h.desc, G, h.Q}, h.total_q, h.scan_tmp, s);
+  if (e != hipSuccess) return e;
+  e = device_scan<Triple>(NodeIn{h.desc, G, h.Q}, NodeOut{h.desc, G, h.C, h.SB}, h.total_r,
+                          reinterpret_cast<Triple*>(h.scan_tmp), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_plan_sizes, dim3(1), dim3(256), 0, s, dhdr);
+  return hipGetLastError();
+}
+
+// the rest: heavy table, lane plan, count pass, offsets
+hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* t, hipStream_t s) {
+  const uint32_t cap = stream_grid_cap();
+  hipLaunchKernelGGL(k_heavy_table, dim3(grid_for(h.cap_nh, 256, cap)), dim3(256), 0, s, dhdr);
+  hipLaunchKernelGGL(k_lane_plan, dim3(grid_for(h.total_r, 256, cap)), dim3(256), 0, s, dhdr);
+  hipLaunchKernelGGL(k_lane_groups, dim3(grid_for(h.cap_nl / kLaneGroup, 256, cap)), dim3(256), 0, s, dhdr);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
+  hipLaunchKernelGGL((k_lanes<false>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
+                     static_cast<uint2*>(nullptr), 0ull, 0ull);
+  hipError_t e = device_scan<uint64_t>(CntIn{h.lane_cnt, h.cap_nl}, OffOut{h.lane_pos}, h.cap_nl + 1,
+                                       h.lane_scan_tmp, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_graph_edges, dim3(grid_for(h.G, 256, cap)), dim3(256), 0, s, dhdr, h.m_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_write(WsHeader* dhdr, const cl_tuning* t, uint32_t* edges, uint64_t lo, uint64_t hi,
+                        uint64_t* graph_offsets, uint32_t G, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
+  hipLaunchKernelGGL((k_lanes<true>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
+                     reinterpret_cast<uint2*>(edges), lo, hi);
+  (void)G;
+  if (graph_offsets) hipLaunchKernelGGL(k_graph_offsets, dim3(16), dim3(256), 0, s, dhdr, graph_offsets);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cl_version(void) { return "clgen 1.0 (gfx950)"; }
+
+uint32_t cl_device_cus(void) { return cus_of_current_device(); }
+
+// ------------------------------------------------------------ exact sum
+cl_status cl_weight_sum_workspace(uint64_t n, uint64_t* bytes_out) {
+  (void)n;
+  if (!bytes_out) return CL_ERR_INVALID_ARG;
+  *bytes_out = align_up(sizeof(GraphDesc)) + align_up(16ull * kBins) + kAlign;
+  return CL_OK;
+}
+
+cl_status cl_weight_sum(const double* w, uint64_t n, void* ws, uint64_t ws_bytes, double* S_out, void* stream) {
+  if (!S_out || (n > 0 && !w)) return CL_ERR_INVALID_ARG;
+  if (n >= 4294967296ull) return CL_ERR_TOO_LARGE;
+  uint64_t need = 0;
+  cl_weight_sum_workspace(n, &need);
+  if (!ws || ws_bytes < need) return CL_ERR_WORKSPACE;
+  if (n == 0) {
+    *S_out = 0.0;
+    return CL_OK;
+  }
+  hipStream_t s = as_stream(stream);
+  char* base = static_cast<char*>(ws);
+  GraphDesc* d = reinterpret_cast<GraphDesc*>(base);
+  unsigned long long* bins = reinterpret_cast<unsigned long long*>(base + align_up(sizeof(GraphDesc)));
+  double* S_dev = reinterpret_cast<double*>(base + align_up(sizeof(GraphDesc)) + align_up(16ull * kBins));
+  GraphDesc h{};
+  h.w = w;
+  h.n = n;
+  h.S = __builtin_inf();
+  h.q_off = 0;
+  CL_TRY(hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_zero_u64, dim3(16), dim3(256), 0, s, bins, static_cast<uint64_t>(2 * kBins));
+  const uint32_t cap = stream_grid_cap();
+  hipLaunchKernelGGL((k_validate<true>), dim3(grid_for(n + 1, 256, cap)), dim3(256), 0, s, d, 1u, n + 1, bins);
+  hipLaunchKernelGGL(k_sum_finalize, dim3(1), dim3(64), 0, s, bins, S_dev, &d->status);
+  CL_TRY(hipGetLastError());
+  double Sh = 0.0;
+  uint32_t st = 0;
+  CL_TRY(hipMemcpyAsync(&Sh, S_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipMemcpyAsync(&st, &d->status, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipStreamSynchronize(s));
+  st &= ~static_cast<uint32_t>(kStBadS);   // no S given: the w_0 / S conditions do not apply
+  if (st) return status_error(st);
+  *S_out = Sh;
+  return CL_OK;
+}
+
+// ------------------------------------------------------- expected edges
+cl_status cl_expected_edges_workspace(uint64_t n, uint64_t* bytes_out) {
+  if (!bytes_out) return CL_ERR_INVALID_ARG;
+  const uint64_t nt = scan_tiles(n + 1);
+  *bytes_out = align_up(16 * (n + 1)) + align_up(16 * (nt + 8)) + align_up(16 * 4096) + align_up(16);
+  return CL_OK;
+}
+
+cl_status cl_expected_edges(const double* w, uint64_t n, double S, void* ws, uint64_t ws_bytes, double* Em_out,
+                            double* Var_out, void* stream) {
+  if (!Em_out || !Var_out || (n > 0 && !w) || !finite_pos(S)) return CL_ERR_INVALID_ARG;
+  if (n >= 4294967296ull) return CL_ERR_TOO_LARGE;
+  uint64_t need = 0;
+  cl_expected_edges_workspace(n, &need);
+  if (!ws || ws_bytes < need) return CL_ERR_WORKSPACE;
+  if (n == 0) {
+    *Em_out = 0.0;
+    *Var_out = 0.0;
+    return CL_OK;
+  }
+  hipStream_t s = as_stream(stream);
+  char* base = static_cast<char*>(ws);
+  const uint64_t nt = scan_tiles(n + 1);
+  Dbl2* suf = reinterpret_cast<Dbl2*>(base);
+  Dbl2* scan_tmp = reinterpret_cast<Dbl2*>(base + align_up(16 * (n + 1)));
+  Dbl2* parts = reinterpret_cast<Dbl2*>(base + align_up(16 * (n + 1)) + align_up(16 * (nt + 8)));
+  Dbl2* out = reinterpret_cast<Dbl2*>(base + align_up(16 * (n + 1)) + align_up(16 * (nt + 8)) + align_up(16 * 4096));
+  CL_TRY((device_scan<Dbl2>(SufIn{w, n}, SufOut{suf, n}, n + 1, scan_tmp, s)));
+  const uint32_t nb = grid_for(n, 256, 4096);
+  hipLaunchKernelGGL(k_expected_edges, dim3(nb), dim3(256), 0, s, w, n, S, suf, parts);
+  hipLaunchKernelGGL(k_reduce_dbl2, dim3(1), dim3(256), 0, s, parts, nb, out);
+  CL_TRY(hipGetLastError());
+  Dbl2 h{};
+  CL_TRY(hipMemcpyAsync(&h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipStreamSynchronize(s));
+  *Em_out = h.a;
+  *Var_out = h.b;
+  return CL_OK;
+}
+
+// ------------------------------------------------------------ partition
+cl_status cl_partition_workspace(uint64_t n, uint32_t P, uint64_t* bytes_out) {
+  if (!bytes_out) return CL_ERR_INVALID_ARG;
+  *bytes_out = align_up(sizeof(GraphDesc)) + align_up(8 * (n + 1)) * 2 + align_up(8 * (scan_tiles(n + 1) + 8)) +
+               align_up(8 * (static_cast<uint64_t>(P) + 1));
+  return CL_OK;
+}
+
+cl_status cl_partition(const double* w, uint64_t n, double S, uint32_t P, void* ws, uint64_t ws_bytes,
+                       uint64_t* bounds_out, uint64_t* total_cost_out, void* stream) {
+  if (!bounds_out || P == 0 || P > (1u << 24) || (n > 0 && !w) || !finite_pos(S)) return CL_ERR_INVALID_ARG;
+  if (n >= 4294967296ull) return CL_ERR_TOO_LARGE;
+  uint64_t need = 0;
+  cl_partition_workspace(n, P, &need);
+  if (!ws || ws_bytes < need) return CL_ERR_WORKSPACE;
+  if (n == 0) {
+    for (uint32_t k = 0; k <= P; ++k) bounds_out[k] = 0;
+    if (total_cost_out) *total_cost_out = 0;
+    return CL_OK;
+  }
+  hipStream_t s = as_stream(stream);
+  char* base = static_cast<char*>(ws);
+  GraphDesc* d = reinterpret_cast<GraphDesc*>(base);
+  uint64_t off = align_up(sizeof(GraphDesc));
+  uint64_t* Q = reinterpret_cast<uint64_t*>(base + off);
+  off += align_up(8 * (n + 1));
+  uint64_t* C = reinterpret_cast<uint64_t*>(base + off);
+  off += align_up(8 * (n + 1));
+  uint64_t* tmp = reinterpret_cast<uint64_t*>(base + off);
+  off += align_up(8 * (scan_tiles(n + 1) + 8));
+  uint64_t* bd = reinterpret_cast<uint64_t*>(base + off);
+  GraphDesc h{};
+  h.w = w;
+  h.n = n;
+  h.S = S;
+  h.u_begin = 0;
+  h.u_end = n;
+  CL_TRY(hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  const uint32_t cap = stream_grid_cap();
+  hipLaunchKernelGGL(k_graph_init, dim3(1), dim3(64), 0, s, d, 1u);
+  hipLaunchKernelGGL((k_validate<false>), dim3(grid_for(n + 1, 256, cap)), dim3(256), 0, s, d, 1u, n + 1,
+                     static_cast<unsigned long long*>(nullptr));
+  CL_TRY((device_scan<uint64_t>(QIn{d, 1u}, QOut{d, 1u, Q}, n + 1, tmp, s)));
+  CL_TRY((device_scan<uint64_t>(PartIn{d, Q}, PartOut{C}, n + 1, tmp, s)));
+  hipLaunchKernelGGL(k_part_bounds, dim3(grid_for(static_cast<uint64_t>(P) + 1, 256, 1024)), dim3(256), 0, s, C, n,
+                     P, bd);
+  CL_TRY(hipGetLastError());
+  uint32_t st = 0;
+  uint64_t Z = 0;
+  CL_TRY(hipMemcpyAsync(bounds_out, bd, 8 * (static_cast<uint64_t>(P) + 1), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipMemcpyAsync(&st, &d->status, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipMemcpyAsync(&Z, C + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipStreamSynchronize(s));
+  if (st) return status_error(st);
+  if (total_cost_out) *total_cost_out = Z;
+  return CL_OK;
+}
+
+// ----------------------------------------------------------- generation
+cl_status cl_workspace_size(const cl_graph* g, uint32_t G, const cl_tuning* t, uint64_t* fixed_bytes,
+                            uint64_t* estimate_bytes) {
+  cl_status st = check_graphs(g, G);
+  if (st != CL_OK) return st;
+  const FixedLayout F = fixed_layout(g, G);
+  // estimate: lanes ~ (S/2 + 2 n_range) / budget per task, heavy segments ~ S / 512
+  const uint64_t bu = budget_units(t) / kCostUnit;
+  double nl = 0.0, nh = 0.0;
+  for (uint32_t i = 0; i < G; ++i) {
+    const double nr = static_cast<double>(g[i].u_end - g[i].u_begin);
+    nl += (g[i].S * 0.5 + 2.0 * nr) / static_cast<double>(bu) + kLaneGroup;
+    nh += g[i].S / 256.0 + 64.0;
+  }
+  const VarLayout V = var_layout(F.bytes, static_cast<uint64_t>(nh), static_cast<uint64_t>(nl) / kLaneGroup * kLaneGroup + kLaneGroup * G);
+  if (fixed_bytes) *fixed_bytes = F.bytes;
+  if (estimate_bytes) *estimate_bytes = V.bytes;
+  return CL_OK;
+}
+
+cl_status cl_count(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes, uint64_t* m_out,
+                   uint64_t* ws_required, void* stream) {
+  cl_status st = check_graphs(g, G);
+  if (st != CL_OK) return st;
+  if (!m_out) return CL_ERR_INVALID_ARG;
+  const FixedLayout F = fixed_layout(g, G);
+  if (ws_required) *ws_required = F.bytes;
+  if (!ws || ws_bytes < F.bytes) return CL_ERR_WORKSPACE;
+  hipStream_t s = as_stream(stream);
+  char* base = static_cast<char*>(ws);
+  WsHeader* dhdr = reinterpret_cast<WsHeader*>(base);
+
+  std::vector<GraphDesc> desc(G);
+  uint64_t qo = 0, ro = 0;
+  const uint64_t bu = budget_units(t);
+  for (uint32_t i = 0; i < G; ++i) {
+    GraphDesc d{};
+    d.w = g[i].w;
+    d.n = g[i].n;
+    d.S = g[i].S;
+    d.seed = g[i].seed;
+    d.u_begin = g[i].u_begin;
+    d.u_end = g[i].u_end;
+    d.q_off = qo;
+    d.r_off = ro;
+    d.budget = bu;
+    qo += g[i].n + 1;
+    ro += (g[i].u_end - g[i].u_begin) + 1;
+    desc[i] = d;
+  }
+  WsHeader h{};
+  h.magic = kWsMagic;
+  h.G = G;
+  h.total_q = F.total_q;
+  h.total_r = F.total_r;
+  h.cap_nh = 0;
+  h.cap_nl = 0;
+  h.bytes_fixed = F.bytes;
+  h.desc = reinterpret_cast<GraphDesc*>(base + F.off_desc);
+  h.Q = reinterpret_cast<uint64_t*>(base + F.off_Q);
+  h.C = reinterpret_cast<uint64_t*>(base + F.off_C);
+  h.SB = reinterpret_cast<uint64_t*>(base + F.off_SB);
+  h.scan_tmp = reinterpret_cast<uint64_t*>(base + F.off_scan);
+  h.scan_tmp_elems = F.scan_elems;
+  h.m_dev = reinterpret_cast<uint64_t*>(base + F.off_m);
+  CL_TRY(hipMemcpyAsync(h.desc, desc.data(), sizeof(GraphDesc) * G, hipMemcpyHostToDevice, s));
+  CL_TRY(hipMemcpyAsync(dhdr, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  CL_TRY(launch_plan_front(dhdr, h, G, s));
+  WsHeader back{};
+  CL_TRY(hipMemcpyAsync(&back, dhdr, sizeof(back), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipStreamSynchronize(s));
+  if (back.status) return status_error(back.status);
+
+  const VarLayout V = var_layout(F.bytes, back.total_nh, back.total_nl);
+  if (ws_required) *ws_required = V.bytes;
+  if (ws_bytes < V.bytes) return CL_ERR_WORKSPACE;
+  h.cap_nh = back.total_nh;
+  h.cap_nl = back.total_nl;
+  h.total_nh = back.total_nh;
+  h.total_nl = back.total_nl;
+  h.bytes_total = V.bytes;
+  h.hseg = reinterpret_cast<uint32_t*>(base + V.off_hseg);
+  h.lane_start = reinterpret_cast<uint2*>(base + V.off_lstart);
+  h.lane_cnt = reinterpret_cast<uint32_t*>(base + V.off_lcnt);
+  h.lane_pos = reinterpret_cast<uint64_t*>(base + V.off_lpos);
+  h.lane_scan_tmp = reinterpret_cast<uint64_t*>(base + V.off_lscan);
+  h.group_graph = reinterpret_cast<uint32_t*>(base + V.off_groups);
+  h.status = 0;
+  h.queue = 0;
+  h.planned = 0;
+  CL_TRY(hipMemcpyAsync(dhdr, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  CL_TRY(launch_plan_back(dhdr, h, t, s));
+  CL_TRY(hipMemcpyAsync(m_out, h.m_dev, 8ull * G, hipMemcpyDeviceToHost, s));
+  CL_TRY(hipMemcpyAsync(&back, dhdr, sizeof(back), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipStreamSynchronize(s));
+  if (back.status) return status_error(back.status);
+  const uint32_t one = 1;
+  CL_TRY(hipMemcpyAsync(&dhdr->planned, &one, sizeof(one), hipMemcpyHostToDevice, s));
+  CL_TRY(hipStreamSynchronize(s));
+  return CL_OK;
+}
+
+cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t edge_begin, uint64_t cap,
+                      uint64_t* graph_offsets, void* stream) {
+  if (!ws || (cap > 0 && !edges)) return CL_ERR_INVALID_ARG;
+  if (edge_begin + cap < edge_begin) return CL_ERR_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  WsHeader* dhdr = static_cast<WsHeader*>(ws);
+  // G for the offsets kernel: read from the header (the launch covers up to 2^20 tasks)
+  CL_TRY(launch_write(dhdr, t, edges, edge_begin, edge_begin + cap, graph_offsets, 1u << 20, s));
+  return CL_OK;
+}
+
+cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments, uint64_t* edges, void* stream) {
+  if (!ws) return CL_ERR_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  WsHeader back{};
+  CL_TRY(hipMemcpyAsync(&back, ws, sizeof(back), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipStreamSynchronize(s));
+  if (back.magic != kWsMagic) return CL_ERR_NOT_PLANNED;
+  if (lanes) *lanes = back.total_nl;
+  if (heavy_segments) *heavy_segments = back.total_nh;
+  if (edges) *edges = back.total_m;
+  if (back.status) return status_error(back.status);
+  if (!back.planned) return CL_ERR_NOT_PLANNED;
+  return CL_OK;
+}
+
+cl_status cl_hash_edges(const uint32_t* edges, uint64_t m, uint64_t index_base, uint64_t* acc, void* stream) {
+  if (!acc || (m > 0 && !edges)) return CL_ERR_INVALID_ARG;
+  if (m == 0) return CL_OK;
+  hipStream_t s = as_stream(stream);
+  hipLaunchKernelGGL(k_hash, dim3(grid_for(m, 256, stream_grid_cap())), dim3(256), 0, s,
+                     reinterpret_cast<const uint2*>(edges), m, index_base, reinterpret_cast<unsigned long long*>(acc));
+  return hip_status(hipGetLastError());
+}
+
+// ----------------------------------------------------------- batch graph
+cl_status cl_batch_capture(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint32_t* edges,
+                           uint64_t cap, uint64_t* graph_offsets, void** graph_exec_out, void* stream) {
+  cl_status st = check_graphs(g, G);
+  if (st != CL_OK) return st;
+  if (!ws || !graph_exec_out || !stream || (cap > 0 && !edges)) return CL_ERR_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  WsHeader* dhdr = static_cast<WsHeader*>(ws);
+  WsHeader h{};
+  CL_TRY(hipMemcpyAsync(&h, dhdr, sizeof(h), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipStreamSynchronize(s));
+  if (h.magic != kWsMagic || !h.planned) return CL_ERR_NOT_PLANNED;
+  if (h.G != G) return CL_ERR_INVALID_ARG;
+  const FixedLayout F = fixed_layout(g, G);
+  if (F.total_q != h.total_q || F.total_r != h.total_r) return CL_ERR_INVALID_ARG;
+  hipGraph_t graph = nullptr;
+  CL_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t e = launch_plan_front(dhdr, h, G, s);
+  if (e == hipSuccess) e = launch_plan_back(dhdr, h, t, s);
+  if (e == hipSuccess) e = launch_write(dhdr, t, edges, 0, cap, graph_offsets, G, s);
+  hipError_t e2 = hipStreamEndCapture(s, &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return CL_ERR_DEVICE;
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return CL_ERR_DEVICE;
+  *graph_exec_out = reinterpret_cast<void*>(exec);
+  return CL_OK;
+}
+
+cl_status cl_batch_launch(void* graph_exec, void* stream) {
+  if (!graph_exec) return CL_ERR_INVALID_ARG;
+  return hip_status(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(graph_exec), as_stream(stream)));
+}
+
+cl_status cl_batch_destroy(void* graph_exec) {
+  if (!graph_exec) return CL_ERR_INVALID_ARG;
+  return hip_status(hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(graph_exec)));
+}
+
+// ------------------------------------------------------- expected degree
+cl_status cl_expected_degree_workspace(uint64_t n, uint64_t* bytes_out) {
+  if (!bytes_out) return CL_ERR_INVALID_ARG;
+  const uint64_t nt = (n + kEdCols - 1) / kEdCols;
+  const uint64_t nb = (n + 255) / 256;
+  // a, gw (float n each), two float partial planes, A, B (double n), T partials
+  *bytes_out = 2 * align_up(4 * (n + 1)) + 2 * align_up(4 * nt * n + 4) + 2 * align_up(8 * (n + 1)) +
+               align_up(8 * (nb + 1)) + align_up(8);
+  return CL_OK;
+}
+
+namespace {
+struct EdLayout {
+  float *a, *gw, *pA, *pB;
+  double *A, *B, *tp, *T;
+  uint32_t nt, nb;
+};
+
+EdLayout ed_layout(void* ws, uint64_t n) {
+  EdLayout L{};
+  char* base = static_cast<char*>(ws);
+  const uint64_t nt = (n + kEdCols - 1) / kEdCols;
+  const uint64_t nb = (n + 255) / 256;
+  uint64_t off = 0;
+  L.a = reinterpret_cast<float*>(base + off);
+  off += align_up(4 * (n + 1));
+  L.gw = reinterpret_cast<float*>(base + off);
+  off += align_up(4 * (n + 1));
+  L.pA = reinterpret_cast<float*>(base + off);
+  off += align_up(4 * nt * n + 4);
+  L.pB = reinterpret_cast<float*>(base + off);
+  off += align_up(4 * nt * n + 4);
+  L.A = reinterpret_cast<double*>(base + off);
+  off += align_up(8 * (n + 1));
+  L.B = reinterpret_cast<double*>(base + off);
+  off += align_up(8 * (n + 1));
+  L.tp = reinterpret_cast<double*>(base + off);
+  off += align_up(8 * (nb + 1));
+  L.T = reinterpret_cast<double*>(base + off);
+  L.nt = static_cast<uint32_t>(nt);
+  L.nb = static_cast<uint32_t>(nb);
+  return L;
+}
+}  // namespace
+
+cl_status cl_expected_degree(const float* w, uint64_t n, double S, double* d_out, void* ws, uint64_t ws_bytes,
+                             void* stream) {
+  if ((n > 0 && (!w || !d_out)) || !finite_pos(S)) return CL_ERR_INVALID_ARG;
+  if (n > (1ull << 31)) return CL_ERR_TOO_LARGE;
+  uint64_t need = 0;
+  cl_expected_degree_workspace(n, &need);
+  if (!ws || ws_bytes < need) return CL_ERR_WORKSPACE;
+  if (n == 0) return CL_OK;
+  hipStream_t s = as_stream(stream);
+  const EdLayout L = ed_layout(ws, n);
+  const uint32_t nrow = static_cast<uint32_t>((n + kEdRows - 1) / kEdRows);
+  hipLaunchKernelGGL(k_rowscale, dim3(L.nb), dim3(256), 0, s, w, n, S, L.a);
+  hipLaunchKernelGGL(k_expdeg_tile, dim3(nrow, L.nt), dim3(kEdRows), 0, s, w, L.a, n, L.pA);
+  hipLaunchKernelGGL(k_expdeg_rows, dim3(L.nb), dim3(256), 0, s, w, L.a, n, L.nt, L.pA, d_out);
+  return hip_status(hipGetLastError());
+}
+
+cl_status cl_expected_degree_backward(const float* w, uint64_t n, double S, const double* grad_d, int s_depends_on_w,
+                                      float* grad_w, void* ws, uint64_t ws_bytes, void* stream) {
+  if ((n > 0 && (!w || !grad_d || !grad_w)) || !finite_pos(S)) return CL_ERR_INVALID_ARG;
+  if (n > (1ull << 31)) return CL_ERR_TOO_LARGE;
+  uint64_t need = 0;
+  cl_expected_degree_workspace(n, &need);
+  if (!ws || ws_bytes < need) return CL_ERR_WORKSPACE;
+  if (n == 0) return CL_OK;
+  hipStream_t s = as_stream(stream);
+  const EdLayout L = ed_layout(ws, n);
+  const uint32_t nrow = static_cast<uint32_t>((n + kEdRows - 1) / kEdRows);
+  hipLaunchKernelGGL(k_rowscale, dim3(L.nb), dim3(256), 0, s, w, n, S, L.a);
+  hipLaunchKernelGGL(k_gw, dim3(L.nb), dim3(256), 0, s, w, grad_d, n, L.gw);
+  hipLaunchKernelGGL(k_expdeg_bwd_tile, dim3(nrow, L.nt), dim3(kEdRows), 0, s, w, L.a, L.gw, n, L.pA, L.pB);
+  hipLaunchKernelGGL(k_expdeg_bwd_rows, dim3(L.nb), dim3(256), 0, s, w, L.a, grad_d, L.gw, n, L.nt, L.pA, L.pB, L.A,
+                     L.B, L.tp);
+  hipLaunchKernelGGL(k_sum_dbl, dim3(1), dim3(256), 0, s, L.tp, L.nb, L.T);
+  hipLaunchKernelGGL(k_expdeg_grad, dim3(L.nb), dim3(256), 0, s, grad_d, L.A, L.B, L.T, s_depends_on_w, n, S,
+                     grad_w);
+  return hip_status(hipGetLastError());
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Workspace layout of the generator: per-graph descriptors, the quantised
+// weight prefix, per-source cost / segment prefixes, the heavy-segment table
+// and the lane plan.  Shared by the kernels and the host entry points.
+#pragma once
+#include <stdint.h>
+
+namespace cl {
+
+constexpr uint32_t kWsMagic = 0x434C5731u;  // "CLW1"
+constexpr uint32_t kCostUnit = 16;          // lane-plan cost units per expected candidate
+constexpr uint32_t kLaneGroup = 64;         // lanes per work item (one wavefront)
+
+// status bits raised on the device
+enum : uint32_t {
+  kStNonfinite = 1u << 0,
+  kStNegative = 1u << 1,
+  kStUnsorted = 1u << 2,
+  kStBadS = 1u << 3,        // S < w_0, or 0 < w_0 < 2^-960
+  kStCapacity = 1u << 4,    // a size exceeded the capacity frozen in the workspace
+  kStCostOverflow = 1u << 5,
+};
+
+struct GraphDesc {
+  // written by the host
+  const double* w;
+  uint64_t n;
+  double S;
+  uint64_t seed;
+  uint64_t u_begin, u_end;
+  uint64_t q_off;    // first slot of this graph's Q (n + 1 slots)
+  uint64_t r_off;    // first slot of this graph's source prefixes (u_end - u_begin + 1 slots)
+  uint64_t budget;   // lane budget in cost units
+  // written by the device
+  double qscale;     // 2^32 / w_0 (0 when w_0 = 0)
+  uint64_t Qbase, Qend;          // global prefix values at the graph's first / last Q slot
+  uint64_t C0, C1, SB0, SB1, H0, H1;
+  uint64_t H;        // heavy sources (a prefix of the range)
+  uint64_t NH;       // heavy segments
+  uint64_t hs_off;   // first heavy-table entry
+  uint64_t L;        // lanes that carry work
+  uint64_t NL;       // lanes incl. padding to a multiple of 64
+  uint64_t lane_off; // first lane
+  uint64_t m;        // edges
+  uint64_t edge_off; // first edge in the batch output
+  uint32_t status;
+  uint32_t pad;
+};
+
+struct Triple {
+  uint64_t c, k, h;  // cost units, segments, heavy sources
+};
+
+// Pointers into the workspace; copied into the workspace header so that
+// later calls need only the workspace base.
+struct WsHeader {
+  uint32_t magic;
+  uint32_t G;
+  uint64_t total_q, total_r;         // Q slots, source slots
+  uint64_t cap_nh, cap_nl;           // capacities of the variable part (0 = not laid out)
+  uint64_t bytes_fixed, bytes_total;
+  GraphDesc* desc;
+  uint64_t* Q;        // [total_q]
+  uint64_t* C;        // [total_r] exclusive prefix of cost units
+  uint64_t* SB;       // [total_r] exclusive prefix of segment counts
+  uint64_t* scan_tmp; // scan partials
+  uint64_t scan_tmp_elems;
+  uint32_t* hseg;     // [cap_nh] heavy segment starts
+  uint2* lane_start;  // [cap_nl] (u, k) of each lane's first segment
+  uint32_t* lane_cnt; // [cap_nl]
+  uint64_t* lane_pos; // [cap_nl + 1] exclusive prefix of lane_cnt (edge offsets)
+  uint64_t* lane_scan_tmp;
+  uint64_t* m_dev;    // [G]
+  uint32_t* group_graph; // [cap_nl / 64]
+  // device-written totals
+  uint64_t total_nh, total_nl, total_m;
+  uint32_t status;
+  uint32_t queue;
+  uint32_t planned;   // 1 after a successful count
+  uint32_t pad2;
+  double max_cost_check;
+};
+
+}  // namespace cl

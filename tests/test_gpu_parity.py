@@ -1,0 +1,254 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by
+element on seeded inputs; invariants and digests at full size."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1406_1215_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cg():
+    from conftest import gpu_available
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_1406_1215_amd import clgen
+    clgen.lib()
+    return clgen
+
+
+def _to_dev(w):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(w, dtype=np.float64)).to("cuda:0")
+
+
+def _edges_np(t):
+    return t.cpu().numpy().view(np.uint32).reshape(-1, 2)
+
+
+def _gpu_edges(cg, w, S, seed, u0=0, u1=None, tuning=None):
+    wd = _to_dev(w)
+    plan = cg.cl_count([cg.Task(wd, S, seed, u0, u1)], tuning=tuning)
+    e = cg.cl_generate(plan)
+    return _edges_np(e)[: plan.total], plan
+
+
+def test_weight_sum_is_exact(cg):
+    rng = np.random.default_rng(30)
+    cases = [W.config_small(), np.array([1.0]), np.array([1e16, 1.0, 1.0]), np.array([3e-310, 2e-310, 1e-320]),
+             np.sort(rng.pareto(0.7, 100000) * 1e3)[::-1], np.zeros(5), np.array([1e308, 1e308])]
+    for w in cases:
+        wd = _to_dev(w)
+        if not np.all(np.isfinite(np.sum(w))):
+            with pytest.raises(cg.ClError):
+                cg.cl_weight_sum(wd)
+            continue
+        assert cg.cl_weight_sum(wd) == O.exact_sum(w)
+
+
+def test_small_config_bit_exact(cg):
+    w = W.config_small()
+    S = O.exact_sum(w)
+    want, m, h, _ = O.generate(w, S, 1)
+    got, plan = _gpu_edges(cg, w, S, 1)
+    assert plan.m == [m]
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 12345678901234567])
+def test_edge_cases_bit_exact(cg, seed):
+    for i, w in enumerate(W.tiny_cases(seed=40 + seed % 7, count=24)):
+        if w.size == 0 or O.exact_sum(w) == 0.0:
+            continue
+        S = O.exact_sum(w)
+        want, m, _, _ = O.generate(w, S, seed + i)
+        got, plan = _gpu_edges(cg, w, S, seed + i)
+        assert plan.m == [m], (i, w.size)
+        assert np.array_equal(got, want), (i, w.size)
+
+
+def test_zero_weights_and_empty_range(cg):
+    import torch
+    w = np.zeros(10)
+    wd = _to_dev(w)
+    plan = cg.cl_count([cg.Task(wd, 1.0, 3)])
+    assert plan.m == [0]
+    w = W.config_small(n=500)
+    S = O.exact_sum(w)
+    plan = cg.cl_count([cg.Task(_to_dev(w), S, 3, 200, 200)])
+    assert plan.m == [0]
+    _ = torch.cuda.synchronize()
+
+
+def _heavy(n, seed, scale):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.pareto(1.05, n) + 1.0)[::-1] * scale
+
+
+@pytest.mark.parametrize("n,scale,seed", [(20000, 30.0, 1), (60000, 80.0, 2), (5000, 400.0, 3)])
+def test_segmented_sources_bit_exact(cg, n, scale, seed):
+    w = _heavy(n, 50 + seed, scale)
+    S = O.exact_sum(w)
+    K0, _ = O.segments(w, S, 0)
+    assert K0 > 1                      # the head is split into segments
+    want, m, h, _ = O.generate(w, S, seed)
+    got, plan = _gpu_edges(cg, w, S, seed)
+    info = cg.cl_plan_info(plan)
+    assert info["heavy_segments"] > 0
+    assert plan.m == [m]
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("u0,u1", [(0, 1), (0, 777), (500, 4000), (9999, 10000), (3000, 3000)])
+def test_source_ranges_bit_exact(cg, u0, u1):
+    w = W.config_small()
+    S = O.exact_sum(w)
+    want, m, _, _ = O.generate(w, S, 9, u0, u1)
+    got, plan = _gpu_edges(cg, w, S, 9, u0, u1)
+    assert plan.m == [m]
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("tuning", [{"lane_budget": 1}, {"lane_budget": 17}, {"lane_budget": 4096},
+                                    {"lane_budget": 192, "blocks_per_cu": 1}, {"blocks_per_cu": 32}])
+def test_schedule_does_not_change_output(cg, tuning):
+    w = _heavy(30000, 60, 40.0)
+    S = O.exact_sum(w)
+    want, m, _, _ = O.generate(w, S, 4)
+    got, plan = _gpu_edges(cg, w, S, 4, tuning=tuning)
+    assert np.array_equal(got, want)
+
+
+def test_batched_tasks_equal_single_tasks(cg):
+    import torch
+    rng = np.random.default_rng(70)
+    ws = [W.config_small(seed=int(rng.integers(1 << 30)), n=int(rng.integers(2, 3000))) for _ in range(7)]
+    ws += [np.zeros(4), _heavy(8000, 71, 50.0), np.full(64, 64.0)]
+    tasks, wants = [], []
+    for i, w in enumerate(ws):
+        S = O.exact_sum(w) if O.exact_sum(w) > 0 else 1.0
+        e, m, _, _ = O.generate(w, S, 100 + i)
+        wants.append(e)
+        tasks.append(cg.Task(_to_dev(w), S, 100 + i))
+    plan = cg.cl_count(tasks)
+    assert plan.m == [x.shape[0] for x in wants]
+    go = torch.zeros(len(tasks) + 1, dtype=torch.int64, device="cuda:0")
+    e = _edges_np(cg.cl_generate(plan, graph_offsets=go))
+    off = go.cpu().numpy()
+    assert off[-1] == plan.total
+    for i, want in enumerate(wants):
+        assert np.array_equal(e[off[i]:off[i + 1]], want), i
+
+
+def test_write_windows(cg):
+    import torch
+    w = _heavy(40000, 80, 30.0)
+    S = O.exact_sum(w)
+    want, m, _, _ = O.generate(w, S, 6)
+    plan = cg.cl_count([cg.Task(_to_dev(w), S, 6)])
+    cuts = [0, 1, m // 3, m // 3 + 1, (2 * m) // 3, m]
+    parts = []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        parts.append(_edges_np(cg.cl_generate(plan, edge_begin=a, cap=b - a))[: b - a])
+    assert np.array_equal(np.concatenate(parts), want)
+    acc = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    e = cg.cl_generate(plan)
+    cg.cl_hash_edges(e, 0, acc)
+    assert cg.hash_value(acc) == O.hash_edges(want)
+
+
+def test_validation_errors_match_oracle(cg):
+    bad = {
+        "unsorted": (np.array([1.0, 2.0, 0.5]), None),
+        "negative": (np.array([2.0, 1.0, -0.5]), None),
+        "nonfinite": (np.array([np.inf, 1.0]), 5.0),
+        "nan": (np.array([3.0, np.nan]), 5.0),
+        "S below w0": (np.array([5.0, 1.0]), 4.0),
+    }
+    for name, (w, S) in bad.items():
+        S = S if S is not None else 10.0
+        oc = O.validate(w, S)
+        assert oc != 0, name
+        with pytest.raises(cg.ClError) as ei:
+            cg.cl_count([cg.Task(_to_dev(w), S, 1)])
+        assert ei.value.code == oc, name
+
+
+def test_partition_matches_oracle(cg):
+    w = W.config_small()
+    S = O.exact_sum(w)
+    for P in (1, 3, 64, 1000, 20000):
+        b, Z = cg.cl_partition(_to_dev(w), S, P)
+        bo, Zo = O.partition(w, S, P)
+        assert Z == Zo
+        assert b == [int(x) for x in bo]
+    w = np.array([1000.0, 900.0] + [1.0] * 60)
+    S = O.exact_sum(w)
+    b, Z = cg.cl_partition(_to_dev(w), S, 16)
+    bo, Zo = O.partition(w, S, 16)
+    assert b == [int(x) for x in bo]
+
+
+def test_expected_edges_matches_oracle(cg):
+    for w in (W.config_small(), _heavy(20000, 90, 60.0)):
+        S = O.exact_sum(w)
+        E, V = cg.cl_expected_edges(_to_dev(w), S)
+        Eo, Vo = O.expected_edges_closed(w, S)
+        assert abs(E - Eo) <= 1e-10 * Eo
+        assert abs(V - Vo) <= 1e-9 * Vo
+
+
+def test_graph_capture_replays(cg):
+    import torch
+    rng = np.random.default_rng(95)
+    ws = [W.config_small(seed=int(rng.integers(1 << 30)), n=int(rng.integers(100, 5000))) for _ in range(5)]
+    tasks, wants = [], []
+    for i, w in enumerate(ws):
+        S = O.exact_sum(w)
+        wants.append(O.generate(w, S, 7 + i)[0])
+        tasks.append(cg.Task(_to_dev(w), S, 7 + i))
+    plan = cg.cl_count(tasks)
+    s = torch.cuda.Stream()
+    bg = cg.cl_batch_capture(plan, s)
+    want_all = np.concatenate(wants)
+    for rep in range(3):
+        bg.edges.fill_(-1)
+        torch.cuda.synchronize()
+        bg.launch(s)
+        s.synchronize()
+        e = _edges_np(bg.edges)[: plan.total]
+        assert np.array_equal(e, want_all), rep
+        off = bg.graph_offsets.cpu().numpy()
+        assert list(np.diff(off)) == [x.shape[0] for x in wants]
+        x = torch.ones(1000, device="cuda:0").sum()   # eager work between replays
+        assert float(x) == 1000.0
+    bg.close()
+
+
+def test_plain_config_full_size_digest(cg):
+    """n = 1e7 power law: count and digest equal the oracle's; invariants."""
+    import torch
+    w = W.config_plain()
+    S = O.exact_sum(w)
+    wd = _to_dev(w)
+    assert cg.cl_weight_sum(wd) == S
+    plan = cg.cl_count([cg.Task(wd, S, 2)])
+    e = cg.cl_generate(plan)
+    acc = cg.cl_hash_edges(e)
+    _, m, h, _ = O.generate(w, S, 2, want_edges=False)
+    assert plan.m == [m]
+    assert cg.hash_value(acc) == h
+    # sampled windows compared edge by edge with single-source oracle runs
+    en = _edges_np(e)
+    rng = np.random.default_rng(3)
+    qs, Q = O.qscan(w)
+    us = en[:, 0]
+    for u in list(rng.integers(0, 2000, 10)) + list(rng.integers(0, w.size, 20)):
+        want_v = O.node_edges(w, S, 2, int(u), Q=Q, qscale=qs)
+        lo = np.searchsorted(us, u, side="left")
+        hi = np.searchsorted(us, u, side="right")
+        assert np.array_equal(en[lo:hi, 1], want_v), int(u)
