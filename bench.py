@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Throughput of the Chung-Lu generation path on one MI355X.
+
+A step is one pass of the whole generation path over the n = 1e7 power-law
+workload (exponent 2.1, w_min = 10, weights capped at sqrt(S), Philox seed 2),
+inputs resident in HBM: exact sum S, plan (validation, quantised prefix,
+segments, lane plan), count pass, offsets, write pass of every edge.
+`value` is edges generated per second.  Printed as one JSON line, with:
+
+* roofline: the write pass (the kernel replaying Alg. 1 and storing the
+  uint32 pairs), timed live with HIP events on its stream; algorithmic work =
+  visited candidates x the sampling rule's operation count; bound "alu" against
+  256 CU x 64 lanes x 2.4 GHz lane-operations per second;
+* hbm_write: bytes of edges written per second by that kernel against 8 TB/s;
+* batched: 256 uneven graphs in one captured HIP graph vs 256 plain calls;
+* cpu_baseline: the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+OPS_PER_CANDIDATE = 145          # operation count of one candidate step
+PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 3.93e13 lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+HBM_PEAK = 8.0e12                 # bytes/s
+METRIC = "edges/sec generated on 1 MI355X + % HBM write roofline; batched vs plain"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_write_pass_plain_1e7.json")
+KERNEL_SOURCES = ["cl_device.hpp", "cl_kernels.hpp", "cl_plan.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1406_1215_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per launch of the write pass from the committed counter
+    summary, if it was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of 1 GiB (for counter scaling)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single "
+              f"MI355X; see DESIGN.md for how the path would shard)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1406_1215_amd import clgen as cg
+    from paper_1406_1215_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    cg.lib()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    log("bench: generating the n=1e7 workload")
+    w_np = W.config_plain()
+    w = torch.from_numpy(w_np).to(dev)
+    seed = 2
+
+    edges = None
+    plan = None
+
+    def step():
+        nonlocal edges, plan
+        S = cg.cl_weight_sum(w)
+        plan = cg.cl_count([cg.Task(w, S, seed)], ws=plan.ws if plan is not None else None)
+        m = plan.total
+        if edges is None or edges.shape[0] < m:
+            edges = torch.empty((int(m * 1.02) + 1024, 2), dtype=torch.int32, device=dev)
+        ev0.record(stream)
+        cg.cl_generate(plan, edges=edges, cap=m)
+        ev1.record(stream)
+        return m
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} steps")
+    write_ms = []
+    total_edges = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        total_edges += step()
+        ev1.synchronize()
+        write_ms.append(ev0.elapsed_time(ev1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    m = plan.total
+    info = cg.cl_plan_info(plan)
+    cand = info["candidates"]
+    t_write = sum(write_ms) / len(write_ms) / 1e3
+    ms_step = elapsed / args.steps * 1e3
+    value = total_edges / elapsed
+    achieved_ops = cand * OPS_PER_CANDIDATE / t_write
+    traffic = traffic_per_launch()
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "plain CL, n=1e7, power law exponent 2.1, w_min=10, capped at sqrt(S), Philox seed 2",
+                   "n": int(w_np.size), "edges": int(m), "candidates": int(cand), "lanes": info["lanes"],
+                   "heavy_segments": info["heavy_segments"]},
+        "roofline": {
+            "kernel": "write pass (k_lanes<write>)",
+            "bound": "alu",
+            "achieved": achieved_ops / 1e12,
+            "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "Top/s",
+            "frac": achieved_ops / PEAK_LANE_OPS,
+            "traffic": traffic,
+            "ops_per_candidate": OPS_PER_CANDIDATE,
+            "candidates_per_launch": int(cand),
+            "launch_ms": t_write * 1e3,
+        },
+        "hbm_write": {
+            "write_pass_GBps": 8.0 * m / t_write / 1e9,
+            "write_pass_frac_of_8TBps": 8.0 * m / t_write / HBM_PEAK,
+            "whole_step_GBps": 8.0 * total_edges / elapsed / 1e9,
+            "whole_step_frac_of_8TBps": 8.0 * total_edges / elapsed / HBM_PEAK,
+        },
+    }
+
+    if not args.no_batched:
+        result["batched"] = bench_batched(args, cg, W, torch, np, dev)
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = 2 * x.numel() * 8
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = bench_cpu(w_np, seed)
+
+    print(json.dumps(result), flush=True)
+
+
+def bench_batched(args, cg, W, torch, np, dev):
+    """256 uneven graphs: one captured HIP graph (whole path, no host sync)
+    vs 256 separate count + write calls, identical output checked by digest."""
+    log("bench: generating the 256-graph batch")
+    batch = W.config_batch()
+    tasks = []
+    for w_np, sd in batch:
+        wd = torch.from_numpy(w_np).to(dev)
+        tasks.append(cg.Task(wd, cg.cl_weight_sum(wd), sd))
+    # plain: one task per call
+    plans = [None] * len(tasks)
+    bufs = [None] * len(tasks)
+    acc_plain = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def plain_pass(check=False):
+        total = 0
+        base = 0
+        for i, t in enumerate(tasks):
+            p = cg.cl_count([t], ws=plans[i].ws if plans[i] is not None else None)
+            plans[i] = p
+            mi = p.total
+            if bufs[i] is None or bufs[i].shape[0] < mi:
+                bufs[i] = torch.empty((mi + 64, 2), dtype=torch.int32, device=dev)
+            cg.cl_generate(p, edges=bufs[i], cap=mi)
+            if check:
+                cg.cl_hash_edges(bufs[i][:mi], base, acc_plain)
+            base += mi
+            total += mi
+        return total
+
+    plain_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batched_reps):
+        m_plain = plain_pass()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / args.batched_reps
+    acc_plain.zero_()
+    plain_pass(check=True)
+
+    plan = cg.cl_count(tasks)
+    s = torch.cuda.Stream()
+    bg = cg.cl_batch_capture(plan, s, cap=plan.total)
+    with torch.cuda.stream(s):
+        bg.launch(s)
+    s.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batched_reps):
+        bg.launch(s)
+    s.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.batched_reps
+    acc_b = torch.zeros(1, dtype=torch.int64, device=dev)
+    with torch.cuda.stream(s):
+        cg.cl_hash_edges(bg.edges[: plan.total], 0, acc_b, stream=s)
+    s.synchronize()
+    same = cg.hash_value(acc_b) == cg.hash_value(acc_plain) and plan.total == m_plain
+    bg.close()
+    return {
+        "workload": "256 graphs, n log-uniform in [1e3,1e6], exponent U(2,3), mean degree U(4,64)",
+        "edges": int(plan.total),
+        "plain_edges_per_s": m_plain / t_plain,
+        "batched_edges_per_s": plan.total / t_batch,
+        "plain_ms": t_plain * 1e3,
+        "batched_ms": t_batch * 1e3,
+        "speedup": t_plain / t_batch,
+        "identical_output": bool(same),
+    }
+
+
+def bench_cpu(w_np, seed):
+    """The oracle (as it stands) on the first half of the sources by cost
+    (uniform consecutive partition, P = 2, part 0): count + write passes."""
+    import oracle as O
+    S = O.exact_sum(w_np)
+    bounds, _ = O.partition(w_np, S, 2)
+    u1 = int(bounds[1])
+    threads = max(1, min(16, os.cpu_count() or 1))
+    log(f"bench: cpu oracle on sources [0, {u1}) with {threads} threads")
+    t0 = time.perf_counter()
+    _, m, _, _ = O.generate(w_np, S, seed, 0, u1, want_edges=True, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": m / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "sample": f"sources [0, {u1}) of the n=1e7 workload (first of 2 equal-cost partitions), "
+                      f"{m} edges, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

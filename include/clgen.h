@@ -140,10 +140,12 @@ cl_status cl_count(const cl_graph* g /* host, G entries */, uint32_t G, const cl
 cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t edge_begin, uint64_t cap,
                       uint64_t* graph_offsets, void* stream);
 
-/* Totals of the plan in ws (host outputs; synchronises).  lanes includes the
- * padding to whole wavefronts. */
+/* Totals of the plan in ws (host outputs, each may be NULL; synchronises).
+ * lanes includes the padding to whole wavefronts; candidates is the number of
+ * candidates the count pass visited (the "edges + sources" work of Eq. 2-4,
+ * rejections included). */
 cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments, uint64_t* edges,
-                       void* stream);
+                       uint64_t* candidates, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Digest of an edge list: acc += sum_i mix(mix(index_base + i) ^ (u_i 2^32 + v_i))

@@ -69,7 +69,7 @@ def lib():
         "cl_count": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _U64, _U64P,
                          _U64P, _P]),
         "cl_generate": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _U64, _P, _P]),
-        "cl_plan_info": (S, [_P, _U64P, _U64P, _U64P, _P]),
+        "cl_plan_info": (S, [_P, _U64P, _U64P, _U64P, _U64P, _P]),
         "cl_hash_edges": (S, [_P, _U64, _U64, _P, _P]),
         "cl_batch_capture": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _P, _U64,
                                  _P, ctypes.POINTER(ctypes.c_void_p), _P]),
@@ -240,9 +240,11 @@ def cl_generate(plan: Plan, edges: Optional[torch.Tensor] = None, edge_begin: in
 def cl_plan_info(plan_or_ws, stream=None) -> dict:
     L = lib()
     ws = plan_or_ws.ws if isinstance(plan_or_ws, Plan) else plan_or_ws
-    lanes, nh, m = _U64(0), _U64(0), _U64(0)
-    code = L.cl_plan_info(_ptr(ws), ctypes.byref(lanes), ctypes.byref(nh), ctypes.byref(m), _stream(stream))
-    return {"status": code, "lanes": int(lanes.value), "heavy_segments": int(nh.value), "edges": int(m.value)}
+    lanes, nh, m, nc = _U64(0), _U64(0), _U64(0), _U64(0)
+    code = L.cl_plan_info(_ptr(ws), ctypes.byref(lanes), ctypes.byref(nh), ctypes.byref(m), ctypes.byref(nc),
+                          _stream(stream))
+    return {"status": code, "lanes": int(lanes.value), "heavy_segments": int(nh.value), "edges": int(m.value),
+            "candidates": int(nc.value)}
 
 
 def cl_hash_edges(edges: torch.Tensor, index_base: int = 0, acc: Optional[torch.Tensor] = None,

@@ -454,7 +454,8 @@ cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t ed
   return CL_OK;
 }
 
-cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments, uint64_t* edges, void* stream) {
+cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments, uint64_t* edges,
+                       uint64_t* candidates, void* stream) {
   if (!ws) return CL_ERR_INVALID_ARG;
   hipStream_t s = as_stream(stream);
   WsHeader back{};
@@ -464,6 +465,7 @@ cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments
   if (lanes) *lanes = back.total_nl;
   if (heavy_segments) *heavy_segments = back.total_nh;
   if (edges) *edges = back.total_m;
+  if (candidates) *candidates = back.total_cand;
   if (back.status) return status_error(back.status);
   if (!back.planned) return CL_ERR_NOT_PLANNED;
   return CL_OK;

@@ -199,7 +199,10 @@ __global__ void k_sum_finalize(const unsigned long long* bins, double* S_out, ui
 // starts from a clean state)
 __global__ void k_reset_status(WsHeader* hdr) {
   for (uint32_t g = threadIdx.x; g < hdr->G; g += blockDim.x) hdr->desc[g].status = 0;
-  if (threadIdx.x == 0) hdr->status = 0;
+  if (threadIdx.x == 0) {
+    hdr->status = 0;
+    hdr->total_cand = 0;
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -459,7 +462,7 @@ struct LaneCtx {
 // segment opens the next one at the top of the loop.
 template <class Emit>
 __device__ __forceinline__ void run_lane(const LaneCtx& cx, const RoundKeys& rk, uint32_t u, uint32_t k,
-                                         uint32_t ue, uint32_t ke, Emit& emit) {
+                                         uint32_t ue, uint32_t ke, Emit& emit, uint32_t& visits) {
   bool more = (u < ue) || (u == ue && k < ke);
   bool inseg = false;
   uint32_t su = 0, sk = 0;   // source and segment of the open segment
@@ -519,6 +522,7 @@ __device__ __forceinline__ void run_lane(const LaneCtx& cx, const RoundKeys& rk,
         }
       }
       if (!stop) {
+        ++visits;
         const double r_acc = unit53(x.x3, x.x2);
         const bool keep = capped ? (q == 1.0 || r_acc * p < q) : (r_acc * p < q);
         if (keep) {
@@ -592,12 +596,19 @@ __global__ void __launch_bounds__(256) k_lanes(WsHeader* hdr, uint2* out, uint64
       if (__any(touches)) {
         uint32_t su = st.x, sk = st.y, eu = en.x, ek = en.y;
         if (!touches) { eu = su; ek = sk; }
-        run_lane(cx, rk, su, sk, eu, ek, em);
+        uint32_t visits = 0;
+        run_lane(cx, rk, su, sk, eu, ek, em, visits);
       }
     } else {
       CountEmit em{0u};
-      run_lane(cx, rk, st.x, st.y, en.x, en.y, em);
+      uint32_t visits = 0;
+      run_lane(cx, rk, st.x, st.y, en.x, en.y, em, visits);
       hdr->lane_cnt[l] = em.c;
+      // candidates visited by the wavefront (statistics of the cost model)
+      uint64_t vs = visits;
+      for (int dd = 32; dd >= 1; dd >>= 1) vs += shfl_idx64(vs, lane ^ dd);
+      if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->total_cand),
+                               static_cast<unsigned long long>(vs));
     }
   }
 }

@@ -73,6 +73,7 @@ struct WsHeader {
   uint32_t* group_graph; // [cap_nl / 64]
   // device-written totals
   uint64_t total_nh, total_nl, total_m;
+  uint64_t total_cand;  // candidates visited by the count pass
   uint32_t status;
   uint32_t queue;
   uint32_t planned;   // 1 after a successful count
