@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--n", type=int, default=10_000_000, help="sources of the plain workload")
+    ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (for counter scaling)")
     return ap.parse_args()
@@ -92,7 +94,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     log("bench: generating the n=1e7 workload")
-    w_np = W.config_plain()
+    w_np = W.config_plain(n=args.n)
     w = torch.from_numpy(w_np).to(dev)
     seed = 2
 
@@ -102,8 +104,12 @@ def main():
     def step():
         nonlocal edges, plan
         S = cg.cl_weight_sum(w)
+        if args.verbose:
+            log(f"bench: S = {S}")
         plan = cg.cl_count([cg.Task(w, S, seed)], ws=plan.ws if plan is not None else None)
         m = plan.total
+        if args.verbose:
+            log(f"bench: counted {m} edges")
         if edges is None or edges.shape[0] < m:
             edges = torch.empty((int(m * 1.02) + 1024, 2), dtype=torch.int32, device=dev)
         ev0.record(stream)
@@ -150,7 +156,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "plain CL, n=1e7, power law exponent 2.1, w_min=10, capped at sqrt(S), Philox seed 2",
+        "config": {"workload": f"plain CL, n={args.n:.0e}, power law exponent 2.1, w_min=10, capped at sqrt(S), "
+                               f"Philox seed 2",
                    "n": int(w_np.size), "edges": int(m), "candidates": int(cand), "lanes": info["lanes"],
                    "heavy_segments": info["heavy_segments"]},
         "roofline": {

@@ -446,14 +446,24 @@ __global__ void __launch_bounds__(256) k_lane_groups(const WsHeader* hdr) {
 // --------------------------------------------------------------------------
 // the per-lane Create-Edges loop
 // --------------------------------------------------------------------------
+// pointers into global memory (address space 1), so that loads through them
+// are global loads rather than generic ones
+template <class T>
+using gptr = const T __attribute__((address_space(1)))*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> to_global(const T* p) {
+  return (gptr<T>)(p);
+}
+
 struct LaneCtx {
-  const double* w;
+  gptr<double> w;
   uint32_t n;
   double S;
   uint32_t u_begin, u_heavy_end;  // sources [u_begin, u_heavy_end) are heavy
-  const uint64_t* SB;             // source prefix of segment counts (graph's r_off applied)
+  gptr<uint64_t> SB;              // source prefix of segment counts (graph's r_off applied)
   uint64_t SB0;
-  const uint32_t* hseg;           // graph's heavy table
+  gptr<uint32_t> hseg;            // graph's heavy table
 };
 
 // Runs the segments of one lane from (u, k) up to (ue, ke) (exclusive) and
@@ -567,10 +577,16 @@ __global__ void __launch_bounds__(256) k_lanes(WsHeader* hdr, uint2* out, uint64
   const GraphDesc* desc = hdr->desc;
   const uint64_t ngroups = hdr->total_nl / kLaneGroup;
   const int lane = threadIdx.x & 63;
+  uint64_t visited = 0;   // candidates visited by this lane over all its work items (count pass)
+  // The loop body has no lane-divergent region that is not closed inside it:
+  // the ticket is fetched by lane 0, broadcast to every lane (so the value is
+  // uniform before readfirstlane marks it so for the compiler), and the only
+  // other single-lane action (the candidate total) is done after the loop.
   while (true) {
     uint32_t grp = 0;
     if (lane == 0) grp = atomicAdd(&hdr->queue, 1u);
     grp = static_cast<uint32_t>(__shfl(static_cast<int>(grp), 0, 64));
+    grp = __builtin_amdgcn_readfirstlane(grp);
     if (grp >= ngroups) break;
     const uint32_t g = hdr->group_graph[grp];
     const GraphDesc& d = desc[g];
@@ -579,14 +595,14 @@ __global__ void __launch_bounds__(256) k_lanes(WsHeader* hdr, uint2* out, uint64
     uint2 en = make_uint2(static_cast<uint32_t>(d.u_end), 0u);
     if (l + 1 < d.lane_off + d.NL) en = hdr->lane_start[l + 1];
     LaneCtx cx;
-    cx.w = d.w;
+    cx.w = to_global(d.w);
     cx.n = static_cast<uint32_t>(d.n);
     cx.S = d.S;
     cx.u_begin = static_cast<uint32_t>(d.u_begin);
     cx.u_heavy_end = static_cast<uint32_t>(d.u_begin + d.H);
-    cx.SB = hdr->SB + d.r_off;
+    cx.SB = to_global(hdr->SB + d.r_off);
     cx.SB0 = d.SB0;
-    cx.hseg = hdr->hseg + d.hs_off;
+    cx.hseg = to_global(hdr->hseg + d.hs_off);
     const RoundKeys rk = philox_round_keys(d.seed);
     if (kWrite) {
       const uint64_t pos0 = hdr->lane_pos[l];
@@ -604,12 +620,14 @@ __global__ void __launch_bounds__(256) k_lanes(WsHeader* hdr, uint2* out, uint64
       uint32_t visits = 0;
       run_lane(cx, rk, st.x, st.y, en.x, en.y, em, visits);
       hdr->lane_cnt[l] = em.c;
-      // candidates visited by the wavefront (statistics of the cost model)
-      uint64_t vs = visits;
-      for (int dd = 32; dd >= 1; dd >>= 1) vs += shfl_idx64(vs, lane ^ dd);
-      if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->total_cand),
-                               static_cast<unsigned long long>(vs));
+      visited += visits;
     }
+  }
+  if (!kWrite) {
+    // candidates visited by the wavefront (statistics of the cost model)
+    for (int dd = 32; dd >= 1; dd >>= 1) visited += shfl_idx64(visited, lane ^ dd);
+    if (lane == 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->total_cand), static_cast<unsigned long long>(visited));
   }
 }
 

@@ -252,3 +252,19 @@ def test_plain_config_full_size_digest(cg):
         lo = np.searchsorted(us, u, side="left")
         hi = np.searchsorted(us, u, side="right")
         assert np.array_equal(en[lo:hi, 1], want_v), int(u)
+
+
+@pytest.mark.parametrize("n", [100_000, 1_000_000])
+def test_plain_shapes_bit_exact(cg, n):
+    """Smaller instances of the n = 1e7 shape (many capped sources at the head);
+    n = 1e5 is the input on which an earlier persistent-loop miscompilation
+    (single-lane tail merged into the loop head) never terminated."""
+    w = W.config_plain(n=n)
+    S = O.exact_sum(w)
+    want, m, _, _ = O.generate(w, S, 2)
+    got, plan = _gpu_edges(cg, w, S, 2)
+    assert plan.m == [m]
+    assert np.array_equal(got, want)
+    info = cg.cl_plan_info(plan)
+    _, _, _, cand = O.generate(w, S, 2, want_edges=False)
+    assert info["candidates"] == cand
