@@ -71,7 +71,7 @@ bool finite_pos(double x) { return x > 0.0 && x <= 1.7976931348623157e308; }
 
 // ---------------------------------------------------------------- layouts
 struct FixedLayout {
-  uint64_t off_desc, off_Q, off_C, off_SB, off_scan, off_m, bytes;
+  uint64_t off_desc, off_Q, off_C, off_SB, off_A, off_scan, off_m, bytes;
   uint64_t total_q, total_r, scan_elems;
 };
 
@@ -94,6 +94,8 @@ FixedLayout fixed_layout(const cl_graph* g, uint32_t G) {
   L.off_C = off;
   off = align_up(off + 8 * tr);
   L.off_SB = off;
+  off = align_up(off + 8 * tr);
+  L.off_A = off;
   off = align_up(off + 8 * tr);
   L.off_scan = off;
   off = align_up(off + 8 * L.scan_elems);
@@ -403,6 +405,7 @@ cl_status cl_count(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, 
   h.Q = reinterpret_cast<uint64_t*>(base + F.off_Q);
   h.C = reinterpret_cast<uint64_t*>(base + F.off_C);
   h.SB = reinterpret_cast<uint64_t*>(base + F.off_SB);
+  h.A = reinterpret_cast<double*>(base + F.off_A);
   h.scan_tmp = reinterpret_cast<uint64_t*>(base + F.off_scan);
   h.scan_tmp_elems = F.scan_elems;
   h.m_dev = reinterpret_cast<uint64_t*>(base + F.off_m);

@@ -56,62 +56,83 @@ __device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
   return Block4{c0, c1, c2, c3};
 }
 
-// 53-bit uniform in (0,1) from two 32-bit words (hi:lo): the odd integer
-// 2*(x >> 12) + 1 < 2^53 times 2^-53; both steps are exact.
+// 53-bit uniform in (0,1) from two 32-bit words (hi:lo): (2*(x >> 12) + 1) * 2^-53.
+// Formed exactly as (1 + k 2^-52) - (1 - 2^-53), k = x >> 12: the first term
+// is k placed in the mantissa of 1.0 and the subtraction is exact (Sterbenz).
 __device__ __forceinline__ double unit53(uint32_t hi, uint32_t lo) {
   const uint64_t x = (static_cast<uint64_t>(hi) << 32) | lo;
-  const uint64_t odd = ((x >> 12) << 1) | 1ull;
-  return static_cast<double>(odd) * 0x1.0p-53;
+  const uint64_t k = x >> 12;
+  const double one_k = __longlong_as_double(static_cast<long long>(k | 0x3FF0000000000000ull));
+  return one_k - 0x1.fffffffffffffp-1;
 }
 
 // ---------------------------------------------------------------------------
 // Logarithms.  ln(m) = 2 atanh(s), s = (m - 1)/(m + 1), and
 // atanh(s)/s = sum_{j>=0} s^{2j}/(2j+1); eleven terms in Horner/FMA form are
 // enough for |s| <= 0.1716.
+//
+// The coefficients 1/(2j+1) (rounded to nearest) live in constant memory and
+// are read once per kernel into scalar registers, so each Horner step is one
+// v_fma_f64 with a scalar addend.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double atanh_series(double z) {
-  // coefficients 1/(2j+1) rounded to nearest, j = 10 down to 0
-  double r = 1.0 / 21.0;
-  r = __builtin_fma(r, z, 1.0 / 19.0);
-  r = __builtin_fma(r, z, 1.0 / 17.0);
-  r = __builtin_fma(r, z, 1.0 / 15.0);
-  r = __builtin_fma(r, z, 1.0 / 13.0);
-  r = __builtin_fma(r, z, 1.0 / 11.0);
-  r = __builtin_fma(r, z, 1.0 / 9.0);
-  r = __builtin_fma(r, z, 1.0 / 7.0);
-  r = __builtin_fma(r, z, 1.0 / 5.0);
-  r = __builtin_fma(r, z, 1.0 / 3.0);
-  r = __builtin_fma(r, z, 1.0);
-  return r;
+__constant__ double kSeries[11] = {1.0,        1.0 / 3.0,  1.0 / 5.0,  1.0 / 7.0,  1.0 / 9.0, 1.0 / 11.0,
+                                   1.0 / 13.0, 1.0 / 15.0, 1.0 / 17.0, 1.0 / 19.0, 1.0 / 21.0};
+
+struct Series {
+  double c[11];
+};
+
+__device__ __forceinline__ Series load_series() {
+  Series sr;
+#pragma unroll
+  for (int j = 0; j < 11; ++j) sr.c[j] = kSeries[j];
+  return sr;
 }
 
-// natural log of a normal x in (0, 1]: split x = m 2^e (m in [1,2)); fold m
-// above sqrt(2) into (0.707, 1] with e + 1; then e ln2 + 2 s P(s^2).
-__device__ __forceinline__ double ln_unit(double x) {
+// 2 s P(s^2), P the 11-term series in Horner form from the top coefficient
+__device__ __forceinline__ double two_s_series(double s, const Series& sr) {
+  const double z = s * s;
+  double r = sr.c[10];
+#pragma unroll
+  for (int j = 9; j >= 0; --j) r = __builtin_fma(r, z, sr.c[j]);
+  return (2.0 * s) * r;
+}
+
+// split a normal x into m in (0.707, 1.414] and e with x = m 2^e
+__device__ __forceinline__ void log_reduce(double x, double& m, int& e) {
   const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(x));
-  int e = static_cast<int>((bits >> 52) & 0x7FF) - 1023;
-  double m = __longlong_as_double(static_cast<long long>((bits & 0x000FFFFFFFFFFFFFull) |
-                                                         0x3FF0000000000000ull));
+  e = static_cast<int>((bits >> 52) & 0x7FF) - 1023;
+  m = __longlong_as_double(static_cast<long long>((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
   if (m > 0x1.6a09e667f3bcdp+0) {  // sqrt(2) rounded to nearest
     m = m * 0.5;
     e = e + 1;
   }
+}
+
+// natural log of a normal x in (0, 1]: e ln2 + 2 s P(s^2), s = (m-1)/(2+(m-1))
+__device__ __forceinline__ double ln_unit(double x, const Series& sr) {
+  double m;
+  int e;
+  log_reduce(x, m, e);
   const double f = m - 1.0;
-  const double s = f / (2.0 + f);
-  const double z = s * s;
-  const double l = (2.0 * s) * atanh_series(z);
+  const double l = two_s_series(f / (2.0 + f), sr);
   return (static_cast<double>(e) * 0x1.62e42fefa39efp-1) + l;  // ln 2 rounded to nearest
 }
 
 // ln(1 - p) for p in (0,1): for p < 1/4, -2 atanh(p/(2-p)) (no cancellation);
-// otherwise ln of the rounded 1 - p.
-__device__ __forceinline__ double ln_one_minus(double p) {
-  if (p < 0.25) {
-    const double s = p / (2.0 - p);
-    const double z = s * s;
-    return -((2.0 * s) * atanh_series(z));
-  }
-  return ln_unit(1.0 - p);
+// otherwise ln of the rounded 1 - p.  Both cases share one division and one
+// series: for small p the quotient is formed as (-p)/(2-p), which is exactly
+// the negated p/(2-p), so 2 s P(s^2) comes out with the sign of -2 atanh.
+__device__ __forceinline__ double ln_one_minus(double p, const Series& sr) {
+  const bool small = p < 0.25;
+  double m;
+  int e;
+  log_reduce(1.0 - p, m, e);
+  const double f = m - 1.0;
+  const double num = small ? -p : f;
+  const double den = small ? (2.0 - p) : (2.0 + f);
+  const double l = two_s_series(num / den, sr);
+  return small ? l : ((static_cast<double>(e) * 0x1.62e42fefa39efp-1) + l);
 }
 
 __device__ __forceinline__ double cap1(double x) { return (x < 1.0) ? x : 1.0; }

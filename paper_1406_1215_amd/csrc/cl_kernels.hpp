@@ -403,7 +403,9 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
     const GraphDesc& d = desc[g];
     const uint64_t r = i - d.r_off;
     const uint64_t nr = d.u_end - d.u_begin;
-    if (r >= nr || d.L == 0) continue;
+    if (r >= nr) continue;
+    hdr->A[i] = d.w[d.u_begin + r] / d.S;   // a_u of Alg. 1, once per source
+    if (d.L == 0) continue;
     const uint64_t L = d.L;
     const uint64_t Z = d.C1 - d.C0;
     const uint64_t cex = hdr->C[i] - d.C0;
@@ -456,10 +458,24 @@ __device__ __forceinline__ gptr<T> to_global(const T* p) {
   return (gptr<T>)(p);
 }
 
+// wave-uniform copies of values that are equal on every lane (they then live
+// in scalar registers)
+__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+  return (static_cast<uint64_t>(uni32(static_cast<uint32_t>(x >> 32))) << 32) | uni32(static_cast<uint32_t>(x));
+}
+__device__ __forceinline__ double unif64(double x) {
+  return __longlong_as_double(static_cast<long long>(uni64(static_cast<uint64_t>(__double_as_longlong(x)))));
+}
+template <class T>
+__device__ __forceinline__ const T* uniptr(const T* p) {
+  return reinterpret_cast<const T*>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+
 struct LaneCtx {
   gptr<double> w;
+  gptr<double> A;                 // a_u = w_u / S of the range's sources (index u - u_begin)
   uint32_t n;
-  double S;
   uint32_t u_begin, u_heavy_end;  // sources [u_begin, u_heavy_end) are heavy
   gptr<uint64_t> SB;              // source prefix of segment counts (graph's r_off applied)
   uint64_t SB0;
@@ -471,8 +487,8 @@ struct LaneCtx {
 // All lanes of the wavefront iterate together; a lane that has finished its
 // segment opens the next one at the top of the loop.
 template <class Emit>
-__device__ __forceinline__ void run_lane(const LaneCtx& cx, const RoundKeys& rk, uint32_t u, uint32_t k,
-                                         uint32_t ue, uint32_t ke, Emit& emit, uint32_t& visits) {
+__device__ __forceinline__ void run_lane(const LaneCtx& cx, const RoundKeys& rk, const Series& sr, uint32_t u,
+                                         uint32_t k, uint32_t ue, uint32_t ke, Emit& emit, uint32_t& visits) {
   bool more = (u < ue) || (u == ue && k < ke);
   bool inseg = false;
   uint32_t su = 0, sk = 0;   // source and segment of the open segment
@@ -482,11 +498,10 @@ __device__ __forceinline__ void run_lane(const LaneCtx& cx, const RoundKeys& rk,
     if (!inseg && more) {
       su = u;
       sk = k;
-      const double wu = cx.w[u];
-      a = wu / cx.S;
+      const uint32_t r = u - cx.u_begin;
+      a = cx.A[r];
       uint32_t K = 1;
       if (u < cx.u_heavy_end) {
-        const uint64_t r = u - cx.u_begin;
         const uint64_t sb = cx.SB[r] - cx.SB0;
         K = static_cast<uint32_t>(cx.SB[r + 1] - cx.SB[r]);
         j = cx.hseg[sb + k];
@@ -522,7 +537,7 @@ __device__ __forceinline__ void run_lane(const LaneCtx& cx, const RoundKeys& rk,
         q = cap1(a * wv_c);
       } else {
         const double r_skip = unit53(x.x1, x.x0);
-        const double ratio = ln_unit(r_skip) / ln_one_minus(p);
+        const double ratio = ln_unit(r_skip, sr) / ln_one_minus(p, sr);
         if (!(ratio < static_cast<double>(send - j))) {
           stop = true;
           q = 0.0;
@@ -559,23 +574,66 @@ struct CountEmit {
   }
 };
 
+// Write-pass output through LDS: every lane stages its edges in 64-byte
+// chunks of the output (8 pairs, aligned to the window start) and stores a
+// chunk once it is complete, as four 16-byte stores, so that HBM receives
+// whole 64-byte sectors instead of the 8-byte pieces of 64 interleaved lane
+// streams.  Chunks a lane shares with its neighbours (its first and last) are
+// stored pair by pair.  LDS layout [slot][thread] keeps the per-emission
+// stores of a wavefront free of bank conflicts.
+constexpr int kStageSlots = 8;
+
 struct WriteEmit {
-  uint2* out;
-  uint64_t pos, lo, hi;
+  uint2* stage;      // LDS, kStageSlots x blockDim entries
+  uint32_t tid;      // thread in block
+  uint32_t nthr;     // blockDim.x
+  uint2* out;        // output window: out[i] is position lo + i
+  uint64_t pos, lo, hi, first;
+  __device__ uint2& slot(uint64_t q) { return stage[(q & (kStageSlots - 1)) * nthr + tid]; }
+  __device__ void flush(uint64_t q0, uint64_t qend) {
+    // chunk [q0, q0 + 8) of the window; the lane owns entries [max(q0, first), qend)
+    const uint64_t f = (first > lo) ? first - lo : 0;
+    const uint64_t s0 = (q0 > f) ? q0 : f;
+    if (s0 == q0 && qend == q0 + kStageSlots) {
+      uint4* dst = reinterpret_cast<uint4*>(out + q0);
+#pragma unroll
+      for (int i = 0; i < kStageSlots / 2; ++i) {
+        const uint2 x0 = stage[(2 * i) * nthr + tid];
+        const uint2 x1 = stage[(2 * i + 1) * nthr + tid];
+        dst[i] = make_uint4(x0.x, x0.y, x1.x, x1.y);
+      }
+    } else {
+      for (uint64_t q = s0; q < qend; ++q) out[q] = slot(q);
+    }
+  }
   __device__ bool operator()(uint32_t u, uint32_t v) {
     if (pos >= hi) return false;
-    if (pos >= lo) out[pos - lo] = make_uint2(u, v);
+    if (pos >= lo) {
+      const uint64_t q = pos - lo;
+      slot(q) = make_uint2(u, v);
+      if ((q & (kStageSlots - 1)) == kStageSlots - 1) flush(q - (kStageSlots - 1), q + 1);
+    }
     ++pos;
     return true;
+  }
+  // the lane's last, incomplete chunk
+  __device__ void finish() {
+    const uint64_t end = (pos < hi) ? pos : hi;
+    if (end > lo) {
+      const uint64_t q = end - lo;
+      if (q & (kStageSlots - 1)) flush(q & ~static_cast<uint64_t>(kStageSlots - 1), q);
+    }
   }
 };
 
 template <bool kWrite>
 __global__ void __launch_bounds__(256) k_lanes(WsHeader* hdr, uint2* out, uint64_t e_lo, uint64_t e_hi) {
+  __shared__ uint2 stage[kWrite ? kStageSlots * 256 : 1];
   if (hdr->status || hdr->magic != kWsMagic) return;
   if (kWrite && !hdr->planned) return;
   const GraphDesc* desc = hdr->desc;
-  const uint64_t ngroups = hdr->total_nl / kLaneGroup;
+  const uint64_t ngroups = uni64(hdr->total_nl) / kLaneGroup;
+  const Series sr = load_series();
   const int lane = threadIdx.x & 63;
   uint64_t visited = 0;   // candidates visited by this lane over all its work items (count pass)
   // The loop body has no lane-divergent region that is not closed inside it:
@@ -586,39 +644,46 @@ __global__ void __launch_bounds__(256) k_lanes(WsHeader* hdr, uint2* out, uint64
     uint32_t grp = 0;
     if (lane == 0) grp = atomicAdd(&hdr->queue, 1u);
     grp = static_cast<uint32_t>(__shfl(static_cast<int>(grp), 0, 64));
-    grp = __builtin_amdgcn_readfirstlane(grp);
+    grp = uni32(grp);
     if (grp >= ngroups) break;
-    const uint32_t g = hdr->group_graph[grp];
+    const uint32_t g = uni32(hdr->group_graph[grp]);
     const GraphDesc& d = desc[g];
+    const uint64_t lane_off = uni64(d.lane_off), NL = uni64(d.NL);
+    const uint32_t u_end = uni32(static_cast<uint32_t>(d.u_end));
     const uint64_t l = static_cast<uint64_t>(grp) * kLaneGroup + lane;
     const uint2 st = hdr->lane_start[l];
-    uint2 en = make_uint2(static_cast<uint32_t>(d.u_end), 0u);
-    if (l + 1 < d.lane_off + d.NL) en = hdr->lane_start[l + 1];
+    uint2 en = make_uint2(u_end, 0u);
+    if (l + 1 < lane_off + NL) en = hdr->lane_start[l + 1];
     LaneCtx cx;
-    cx.w = to_global(d.w);
-    cx.n = static_cast<uint32_t>(d.n);
-    cx.S = d.S;
-    cx.u_begin = static_cast<uint32_t>(d.u_begin);
-    cx.u_heavy_end = static_cast<uint32_t>(d.u_begin + d.H);
-    cx.SB = to_global(hdr->SB + d.r_off);
-    cx.SB0 = d.SB0;
-    cx.hseg = to_global(hdr->hseg + d.hs_off);
-    const RoundKeys rk = philox_round_keys(d.seed);
+    cx.w = to_global(uniptr(d.w));
+    cx.n = uni32(static_cast<uint32_t>(d.n));
+    cx.u_begin = uni32(static_cast<uint32_t>(d.u_begin));
+    cx.u_heavy_end = cx.u_begin + uni32(static_cast<uint32_t>(d.H));
+    const uint64_t r_off = uni64(d.r_off);
+    cx.A = to_global(uniptr(hdr->A) + r_off);
+    cx.SB = to_global(uniptr(hdr->SB) + r_off);
+    cx.SB0 = uni64(d.SB0);
+    cx.hseg = to_global(uniptr(hdr->hseg) + uni64(d.hs_off));
+    const RoundKeys rk = philox_round_keys(uni64(d.seed));
     if (kWrite) {
       const uint64_t pos0 = hdr->lane_pos[l];
       const uint64_t cnt = hdr->lane_cnt[l];
       const bool touches = (pos0 < e_hi) && (pos0 + cnt > e_lo);
-      WriteEmit em{out, pos0, e_lo, e_hi};
       if (__any(touches)) {
+        WriteEmit em{stage, threadIdx.x, blockDim.x, out, pos0, e_lo, e_hi, pos0};
         uint32_t su = st.x, sk = st.y, eu = en.x, ek = en.y;
-        if (!touches) { eu = su; ek = sk; }
+        if (!touches) {
+          eu = su;
+          ek = sk;
+        }
         uint32_t visits = 0;
-        run_lane(cx, rk, su, sk, eu, ek, em, visits);
+        run_lane(cx, rk, sr, su, sk, eu, ek, em, visits);
+        if (touches) em.finish();
       }
     } else {
       CountEmit em{0u};
       uint32_t visits = 0;
-      run_lane(cx, rk, st.x, st.y, en.x, en.y, em, visits);
+      run_lane(cx, rk, sr, st.x, st.y, en.x, en.y, em, visits);
       hdr->lane_cnt[l] = em.c;
       visited += visits;
     }

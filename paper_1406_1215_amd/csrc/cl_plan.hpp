@@ -62,6 +62,7 @@ struct WsHeader {
   uint64_t* Q;        // [total_q]
   uint64_t* C;        // [total_r] exclusive prefix of cost units
   uint64_t* SB;       // [total_r] exclusive prefix of segment counts
+  double* A;          // [total_r] a_u = w_u / S per source of the range
   uint64_t* scan_tmp; // scan partials
   uint64_t scan_tmp_elems;
   uint32_t* hseg;     // [cap_nh] heavy segment starts
