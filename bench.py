@@ -4,14 +4,17 @@
 A step is one pass of the whole generation path over the n = 1e7 power-law
 workload (exponent 2.1, w_min = 10, weights capped at sqrt(S), Philox seed 2),
 inputs resident in HBM: exact sum S, plan (validation, quantised prefix,
-segments, lane plan), count pass, offsets, write pass of every edge.
+segments, lane plan), one pass of every lane into its slot (counting and
+writing), offsets, compaction of the slots into the contiguous edge list.
 `value` is edges generated per second.  Printed as one JSON line, with:
 
-* roofline: the write pass (the kernel replaying Alg. 1 and storing the
-  uint32 pairs), timed live with HIP events on its stream; algorithmic work =
-  visited candidates x the sampling rule's operation count; bound "alu" against
-  256 CU x 64 lanes x 2.4 GHz lane-operations per second;
-* hbm_write: bytes of edges written per second by that kernel against 8 TB/s;
+* roofline: the one-pass generation kernel (Alg. 1 per lane, edges staged
+  into 64-byte chunks of per-lane slots), timed with HIP events on its stream;
+  algorithmic work = visited candidates x the sampling rule's operation count;
+  bound "alu" against 256 CU x 64 lanes x 2.4 GHz lane-operations per second;
+* hbm_write: bytes of edges written per second by that kernel and by the
+  compaction copy, against 8 TB/s;
+* two_pass: the count-then-replay path (count pass, offsets, write pass);
 * batched: 256 uneven graphs in one captured HIP graph vs 256 plain calls;
 * cpu_baseline: the CPU oracle on a bounded sample of the same workload.
 """
@@ -63,6 +66,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-two-pass", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000, help="sources of the plain workload")
     ap.add_argument("--verbose", action="store_true")
@@ -98,18 +102,19 @@ def main():
     w = torch.from_numpy(w_np).to(dev)
     seed = 2
 
+    # one-pass path (the default): S, plan + one pass into slots, compaction
     edges = None
     plan = None
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
 
     def step():
         nonlocal edges, plan
         S = cg.cl_weight_sum(w)
-        if args.verbose:
-            log(f"bench: S = {S}")
-        plan = cg.cl_count([cg.Task(w, S, seed)], ws=plan.ws if plan is not None else None)
+        plan = cg.cl_sample([cg.Task(w, S, seed)], ws=plan.ws if plan is not None else None)
         m = plan.total
         if args.verbose:
-            log(f"bench: counted {m} edges")
+            log(f"bench: S = {S}, {m} edges")
         if edges is None or edges.shape[0] < m:
             edges = torch.empty((int(m * 1.02) + 1024, 2), dtype=torch.int32, device=dev)
         ev0.record(stream)
@@ -117,31 +122,31 @@ def main():
         ev1.record(stream)
         return m
 
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} steps")
-    write_ms = []
+    copy_ms, lane_ms = [], []
     total_edges = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         total_edges += step()
         ev1.synchronize()
-        write_ms.append(ev0.elapsed_time(ev1))
+        copy_ms.append(ev0.elapsed_time(ev1))
+        lane_ms.append(cg.cl_plan_info(plan)["lane_kernel_ms"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
     m = plan.total
     info = cg.cl_plan_info(plan)
     cand = info["candidates"]
-    t_write = sum(write_ms) / len(write_ms) / 1e3
+    t_gen = sum(lane_ms) / len(lane_ms) / 1e3
+    t_copy = sum(copy_ms) / len(copy_ms) / 1e3
     ms_step = elapsed / args.steps * 1e3
     value = total_edges / elapsed
-    achieved_ops = cand * OPS_PER_CANDIDATE / t_write
+    achieved_ops = cand * OPS_PER_CANDIDATE / t_gen
     traffic = traffic_per_launch()
     result = {
         "metric": METRIC,
@@ -159,9 +164,9 @@ def main():
         "config": {"workload": f"plain CL, n={args.n:.0e}, power law exponent 2.1, w_min=10, capped at sqrt(S), "
                                f"Philox seed 2",
                    "n": int(w_np.size), "edges": int(m), "candidates": int(cand), "lanes": info["lanes"],
-                   "heavy_segments": info["heavy_segments"]},
+                   "heavy_segments": info["heavy_segments"], "path": "one pass into slots + compaction"},
         "roofline": {
-            "kernel": "write pass (k_lanes<write>)",
+            "kernel": "one-pass generation (k_lanes<2>)",
             "bound": "alu",
             "achieved": achieved_ops / 1e12,
             "peak": PEAK_LANE_OPS / 1e12,
@@ -170,15 +175,19 @@ def main():
             "traffic": traffic,
             "ops_per_candidate": OPS_PER_CANDIDATE,
             "candidates_per_launch": int(cand),
-            "launch_ms": t_write * 1e3,
+            "launch_ms": t_gen * 1e3,
         },
         "hbm_write": {
-            "write_pass_GBps": 8.0 * m / t_write / 1e9,
-            "write_pass_frac_of_8TBps": 8.0 * m / t_write / HBM_PEAK,
+            "generation_GBps": 8.0 * m / t_gen / 1e9,
+            "generation_frac_of_8TBps": 8.0 * m / t_gen / HBM_PEAK,
+            "compaction_ms": t_copy * 1e3,
+            "compaction_GBps_read_plus_write": 16.0 * m / t_copy / 1e9,
             "whole_step_GBps": 8.0 * total_edges / elapsed / 1e9,
             "whole_step_frac_of_8TBps": 8.0 * total_edges / elapsed / HBM_PEAK,
         },
     }
+    if not args.no_two_pass:
+        result["two_pass"] = bench_two_pass(args, cg, torch, w, seed, dev, stream)
 
     if not args.no_batched:
         result["batched"] = bench_batched(args, cg, W, torch, np, dev)
@@ -196,6 +205,39 @@ def main():
         result["cpu_baseline"] = bench_cpu(w_np, seed)
 
     print(json.dumps(result), flush=True)
+
+
+def bench_two_pass(args, cg, torch, w, seed, dev, stream):
+    """The count-then-replay path on the same workload: S, plan + count pass,
+    write pass (replay with the same random words) into the output."""
+    edges = None
+    plan = None
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    write_ms, count_ms = [], []
+    reps = max(2, args.steps // 2)
+    total = 0
+    for it in range(reps + 1):
+        if it == 1:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        S = cg.cl_weight_sum(w)
+        plan = cg.cl_count([cg.Task(w, S, seed)], ws=plan.ws if plan is not None else None)
+        m = plan.total
+        if edges is None:
+            edges = torch.empty((int(m * 1.02) + 1024, 2), dtype=torch.int32, device=dev)
+        ev0.record(stream)
+        cg.cl_generate(plan, edges=edges, cap=m)
+        ev1.record(stream)
+        ev1.synchronize()
+        if it >= 1:
+            total += m
+            write_ms.append(ev0.elapsed_time(ev1))
+            count_ms.append(cg.cl_plan_info(plan)["lane_kernel_ms"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"edges_per_s": total / el, "ms_per_step": el / reps * 1e3,
+            "count_kernel_ms": sum(count_ms) / len(count_ms), "write_kernel_ms": sum(write_ms) / len(write_ms)}
 
 
 def bench_batched(args, cg, W, torch, np, dev):
@@ -216,7 +258,7 @@ def bench_batched(args, cg, W, torch, np, dev):
         total = 0
         base = 0
         for i, t in enumerate(tasks):
-            p = cg.cl_count([t], ws=plans[i].ws if plans[i] is not None else None)
+            p = cg.cl_sample([t], ws=plans[i].ws if plans[i] is not None else None)
             plans[i] = p
             mi = p.total
             if bufs[i] is None or bufs[i].shape[0] < mi:
@@ -238,7 +280,7 @@ def bench_batched(args, cg, W, torch, np, dev):
     acc_plain.zero_()
     plain_pass(check=True)
 
-    plan = cg.cl_count(tasks)
+    plan = cg.cl_sample(tasks)
     s = torch.cuda.Stream()
     bg = cg.cl_batch_capture(plan, s, cap=plan.total)
     with torch.cuda.stream(s):

@@ -70,8 +70,9 @@ typedef struct cl_graph {
 typedef struct cl_tuning {
   uint32_t lane_budget;    /* expected candidates per lane (Eq. 5 chunk size), default 192 */
   uint32_t blocks_per_cu;  /* persistent grid = compute units x this, default 8 */
-  uint32_t reserved0;
-  uint32_t reserved1;
+  uint32_t slot_margin;    /* cl_sample slots: 0 = mu + 8 sqrt(mu) + 24 (default); 1 = no margin (tests
+                              of the overflow replay: about half of the lanes overflow) */
+  uint32_t reserved;
 } cl_tuning;
 
 /* ---------------------------------------------------------------------------
@@ -118,18 +119,34 @@ cl_status cl_partition(const double* w, uint64_t n, double S, uint32_t P, void* 
  * receives the bytes the workspace needs; when ws_bytes is smaller the call
  * returns CL_ERR_WORKSPACE without generating (call again with a larger ws).
  * cl_workspace_size gives the size of the part known before the data is seen
- * (fixed_bytes) and an estimate of the whole (estimate_bytes).
+ * (fixed_bytes) and an estimate of the whole (estimate_bytes) for cl_count
+ * (one_pass = 0) or cl_sample (one_pass = 1).
  * Synchronises twice (sizes, counts).
  * ------------------------------------------------------------------------- */
 cl_status cl_workspace_size(const cl_graph* g /* host, G entries */, uint32_t G, const cl_tuning* t,
-                            uint64_t* fixed_bytes /* host */, uint64_t* estimate_bytes /* host */);
+                            uint32_t one_pass, uint64_t* fixed_bytes /* host */,
+                            uint64_t* estimate_bytes /* host */);
 cl_status cl_count(const cl_graph* g /* host, G entries */, uint32_t G, const cl_tuning* t,
                    void* ws, uint64_t ws_bytes, uint64_t* m_out /* host */,
                    uint64_t* ws_required /* host, may be NULL */, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Generation, write pass: replays the planned lanes with the same random
- * words and writes every edge whose position in the batch output lies in
+ * Generation in one pass: the same plan as cl_count, then every lane runs
+ * Alg. 1 once, counting its edges and writing them into its own slot of the
+ * workspace (capacity from the lane's plan cost mu: mu + 8 sqrt(mu) + 24, a
+ * Chernoff margin after Sec. 4, Theorem 2; a lane above it is replayed by
+ * cl_generate).  m_out as for cl_count.  cl_generate then copies the slots to
+ * the output instead of replaying the lanes.  The workspace is larger than
+ * for cl_count by about 1.4 x 8 bytes per expected edge.  Synchronises twice.
+ * ------------------------------------------------------------------------- */
+cl_status cl_sample(const cl_graph* g /* host, G entries */, uint32_t G, const cl_tuning* t,
+                    void* ws, uint64_t ws_bytes, uint64_t* m_out /* host */,
+                    uint64_t* ws_required /* host, may be NULL */, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Generation, write pass: for a plan of cl_count, replays the planned lanes
+ * with the same random words; for a plan of cl_sample, copies the lanes'
+ * slots.  Either way it writes every edge whose position in the batch output lies in
  * [edge_begin, edge_begin + cap) to edges[2 (pos - edge_begin) + {0,1}] as
  * (u, v).  Task g's edges occupy positions [off_g, off_g + m_g), off_g = sum of
  * m_h for h < g.  graph_offsets (device, G + 1 entries, may be NULL) receives
@@ -142,10 +159,12 @@ cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t ed
 
 /* Totals of the plan in ws (host outputs, each may be NULL; synchronises).
  * lanes includes the padding to whole wavefronts; candidates is the number of
- * candidates the count pass visited (the "edges + sources" work of Eq. 2-4,
- * rejections included). */
+ * candidates the lane kernel visited (the "edges + sources" work of Eq. 2-4,
+ * rejections included); lane_kernel_ms is the duration of that kernel
+ * (count pass or one pass), timed by HIP events on the caller's stream;
+ * overflow_lanes counts one-pass lanes that exceeded their slot. */
 cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments, uint64_t* edges,
-                       uint64_t* candidates, void* stream);
+                       uint64_t* candidates, float* lane_kernel_ms, uint32_t* overflow_lanes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Digest of an edge list: acc += sum_i mix(mix(index_base + i) ^ (u_i 2^32 + v_i))
@@ -157,8 +176,9 @@ cl_status cl_hash_edges(const uint32_t* edges, uint64_t m, uint64_t index_base, 
 
 /* ---------------------------------------------------------------------------
  * Batched generation as one replayable HIP graph: records the whole path
- * (validation, prefix, plan, count, offsets, write) for the G tasks planned in
- * ws by a preceding cl_count (same g), with the sizes of that plan, on a
+ * (validation, prefix, plan, count or one pass, offsets, output) for the G
+ * tasks planned in ws by a preceding cl_count or cl_sample (same g), with the
+ * sizes of that plan, on a
  * non-null stream in capture mode.  Each replay regenerates all G edge lists
  * into edges[0 .. 2 cap) with no host synchronisation; graph_offsets (device,
  * G + 1) receives the task offsets.  If a replay finds larger sizes than the

@@ -39,7 +39,7 @@ class cl_graph(ctypes.Structure):
 
 class cl_tuning(ctypes.Structure):
     _fields_ = [("lane_budget", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
-                ("reserved0", ctypes.c_uint32), ("reserved1", ctypes.c_uint32)]
+                ("slot_margin", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -65,11 +65,15 @@ def lib():
         "cl_expected_edges": (S, [_P, _U64, ctypes.c_double, _P, _U64, _DP, _DP, _P]),
         "cl_partition_workspace": (S, [_U64, ctypes.c_uint32, _U64P]),
         "cl_partition": (S, [_P, _U64, ctypes.c_double, ctypes.c_uint32, _P, _U64, _U64P, _U64P, _P]),
-        "cl_workspace_size": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _U64P, _U64P]),
+        "cl_workspace_size": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), ctypes.c_uint32,
+                                  _U64P, _U64P]),
+        "cl_sample": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _U64, _U64P,
+                          _U64P, _P]),
         "cl_count": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _U64, _U64P,
                          _U64P, _P]),
         "cl_generate": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _U64, _P, _P]),
-        "cl_plan_info": (S, [_P, _U64P, _U64P, _U64P, _U64P, _P]),
+        "cl_plan_info": (S, [_P, _U64P, _U64P, _U64P, _U64P, ctypes.POINTER(ctypes.c_float),
+                              ctypes.POINTER(ctypes.c_uint32), _P]),
         "cl_hash_edges": (S, [_P, _U64, _U64, _P, _P]),
         "cl_batch_capture": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _P, _U64,
                                  _P, ctypes.POINTER(ctypes.c_void_p), _P]),
@@ -111,7 +115,8 @@ def _ws(nbytes: int, device) -> torch.Tensor:
 def _tuning(t: Optional[dict]):
     if t is None:
         return None
-    return ctypes.pointer(cl_tuning(int(t.get("lane_budget", 0)), int(t.get("blocks_per_cu", 0)), 0, 0))
+    return ctypes.pointer(cl_tuning(int(t.get("lane_budget", 0)), int(t.get("blocks_per_cu", 0)),
+                                    int(t.get("slot_margin", 0)), 0))
 
 
 def _f64(w: torch.Tensor) -> torch.Tensor:
@@ -198,9 +203,7 @@ def _graph_array(tasks: Sequence[Task]):
     return arr
 
 
-def cl_count(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional[torch.Tensor] = None,
-             stream=None) -> Plan:
-    """Plans the tasks and counts their edges (count pass + offsets)."""
+def _plan(fn_name: str, one_pass: int, tasks: Sequence[Task], tuning, ws, stream) -> Plan:
     L = lib()
     tasks = list(tasks)
     arr = _graph_array(tasks)
@@ -210,16 +213,31 @@ def cl_count(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional[
     if ws is None:
         fixed = _U64(0)
         est = _U64(0)
-        _check(L.cl_workspace_size(arr, G, tun, ctypes.byref(fixed), ctypes.byref(est)), "cl_workspace_size")
+        _check(L.cl_workspace_size(arr, G, tun, one_pass, ctypes.byref(fixed), ctypes.byref(est)),
+               "cl_workspace_size")
         ws = _ws(est.value, dev)
     m = (ctypes.c_uint64 * G)()
     req = _U64(0)
-    code = L.cl_count(arr, G, tun, _ptr(ws), ws.numel(), m, ctypes.byref(req), _stream(stream))
+    fn = getattr(L, fn_name)
+    code = fn(arr, G, tun, _ptr(ws), ws.numel(), m, ctypes.byref(req), _stream(stream))
     if code == -6:
         ws = _ws(req.value, dev)
-        code = L.cl_count(arr, G, tun, _ptr(ws), ws.numel(), m, ctypes.byref(req), _stream(stream))
-    _check(code, "cl_count")
+        code = fn(arr, G, tun, _ptr(ws), ws.numel(), m, ctypes.byref(req), _stream(stream))
+    _check(code, fn_name)
     return Plan(ws=ws, graphs=arr, tasks=tasks, m=[int(x) for x in m], tuning=tuning)
+
+
+def cl_count(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional[torch.Tensor] = None,
+             stream=None) -> Plan:
+    """Plans the tasks and counts their edges (count pass + offsets)."""
+    return _plan("cl_count", 0, tasks, tuning, ws, stream)
+
+
+def cl_sample(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional[torch.Tensor] = None,
+              stream=None) -> Plan:
+    """Plans the tasks and generates them in one pass into per-lane slots of
+    the workspace; cl_generate then copies the slots to the output."""
+    return _plan("cl_sample", 1, tasks, tuning, ws, stream)
 
 
 def cl_generate(plan: Plan, edges: Optional[torch.Tensor] = None, edge_begin: int = 0, cap: Optional[int] = None,
@@ -241,10 +259,12 @@ def cl_plan_info(plan_or_ws, stream=None) -> dict:
     L = lib()
     ws = plan_or_ws.ws if isinstance(plan_or_ws, Plan) else plan_or_ws
     lanes, nh, m, nc = _U64(0), _U64(0), _U64(0), _U64(0)
+    ms = ctypes.c_float(0.0)
+    ov = ctypes.c_uint32(0)
     code = L.cl_plan_info(_ptr(ws), ctypes.byref(lanes), ctypes.byref(nh), ctypes.byref(m), ctypes.byref(nc),
-                          _stream(stream))
+                          ctypes.byref(ms), ctypes.byref(ov), _stream(stream))
     return {"status": code, "lanes": int(lanes.value), "heavy_segments": int(nh.value), "edges": int(m.value),
-            "candidates": int(nc.value)}
+            "candidates": int(nc.value), "lane_kernel_ms": float(ms.value), "overflow_lanes": int(ov.value)}
 
 
 def cl_hash_edges(edges: torch.Tensor, index_base: int = 0, acc: Optional[torch.Tensor] = None,
@@ -343,5 +363,5 @@ def generate(w: torch.Tensor, seed: int, S: Optional[float] = None, u_begin: int
     write.  Returns an (m, 2) int32 tensor of uint32 (u, v) pairs."""
     if S is None:
         S = cl_weight_sum(w)
-    plan = cl_count([Task(w, S, seed, u_begin, u_end)], tuning=tuning)
+    plan = cl_sample([Task(w, S, seed, u_begin, u_end)], tuning=tuning)
     return cl_generate(plan)

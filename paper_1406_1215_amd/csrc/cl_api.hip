@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "clgen.h"
@@ -107,9 +108,11 @@ FixedLayout fixed_layout(const cl_graph* g, uint32_t G) {
 
 struct VarLayout {
   uint64_t off_hseg, off_lstart, off_lcnt, off_lpos, off_lscan, off_groups, bytes;
+  uint64_t off_lcum, off_soff, off_sscan, off_slots, slot_cap;
 };
 
-VarLayout var_layout(uint64_t base, uint64_t nh, uint64_t nl) {
+// nh heavy segments, nl lanes; with one_pass, slot_cap edges of slots
+VarLayout var_layout(uint64_t base, uint64_t nh, uint64_t nl, bool one_pass, uint64_t slot_cap) {
   VarLayout V{};
   uint64_t off = align_up(base);
   V.off_hseg = off;
@@ -124,8 +127,27 @@ VarLayout var_layout(uint64_t base, uint64_t nh, uint64_t nl) {
   off = align_up(off + 8 * (scan_tiles(nl + 1) + 8));
   V.off_groups = off;
   off = align_up(off + 4 * std::max<uint64_t>(nl / kLaneGroup, 1));
+  if (one_pass) {
+    V.off_lcum = off;
+    off = align_up(off + 8 * (nl + 1));
+    V.off_soff = off;
+    off = align_up(off + 8 * (nl + 1));
+    V.off_sscan = off;
+    off = align_up(off + 8 * (scan_tiles(nl + 1) + 8));
+    V.off_slots = off;
+    V.slot_cap = slot_cap;
+    off = align_up(off + 8 * std::max<uint64_t>(slot_cap, 1));
+  }
   V.bytes = off;
   return V;
+}
+
+// upper bound of the slot capacities: sum (mu + 8 sqrt(mu) + 32) over the
+// lanes, with sum sqrt(mu) <= sqrt(lanes * sum mu)
+uint64_t slot_bound(uint64_t total_cost, uint64_t nl) {
+  const double mu = static_cast<double>(total_cost) / kCostUnit;
+  const double b = mu + 8.0 * std::sqrt(static_cast<double>(nl) * mu) + 40.0 * static_cast<double>(nl) + 64.0;
+  return static_cast<uint64_t>(std::ceil(b));
 }
 
 cl_status check_graphs(const cl_graph* g, uint32_t G) {
@@ -166,15 +188,31 @@ hipError_t launch_plan_front(WsHeader* dhdr, const WsHeader& h, uint32_t G, hipS
   return hipGetLastError();
 }
 
-// the rest: heavy table, lane plan, count pass, offsets
-hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* t, hipStream_t s) {
+// the rest: heavy table, lane plan, then either the count pass (two-pass
+// plans) or the one pass into slots, and the offsets
+hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* t, hipStream_t s,
+                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   const uint32_t cap = stream_grid_cap();
   hipLaunchKernelGGL(k_heavy_table, dim3(grid_for(h.cap_nh, 256, cap)), dim3(256), 0, s, dhdr);
   hipLaunchKernelGGL(k_lane_plan, dim3(grid_for(h.total_r, 256, cap)), dim3(256), 0, s, dhdr);
   hipLaunchKernelGGL(k_lane_groups, dim3(grid_for(h.cap_nl / kLaneGroup, 256, cap)), dim3(256), 0, s, dhdr);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
-  hipLaunchKernelGGL((k_lanes<false>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                     static_cast<uint2*>(nullptr), 0ull, 0ull);
+  if (h.mode == 1) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->overflow, 0u);
+    hipError_t e = device_scan<uint64_t>(SlotIn{dhdr, h.cap_nl}, SlotOut{h.slot_off}, h.cap_nl + 1,
+                                         h.slot_scan_tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_slot_check, dim3(1), dim3(1), 0, s, dhdr);
+    if (ev0) (void)hipEventRecord(ev0, s);
+    hipLaunchKernelGGL((k_lanes<2>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
+                       static_cast<uint2*>(nullptr), 0ull, 0ull);
+    if (ev1) (void)hipEventRecord(ev1, s);
+  } else {
+    if (ev0) (void)hipEventRecord(ev0, s);
+    hipLaunchKernelGGL((k_lanes<0>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
+                       static_cast<uint2*>(nullptr), 0ull, 0ull);
+    if (ev1) (void)hipEventRecord(ev1, s);
+  }
   hipError_t e = device_scan<uint64_t>(CntIn{h.lane_cnt, h.cap_nl}, OffOut{h.lane_pos}, h.cap_nl + 1,
                                        h.lane_scan_tmp, s);
   if (e != hipSuccess) return e;
@@ -182,12 +220,17 @@ hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* 
   return hipGetLastError();
 }
 
+// output of a planned workspace into the window [lo, hi): compaction of the
+// slots (one-pass plans) and the replay kernel (every lane for two-pass plans,
+// only overflowed lanes for one-pass plans); each kernel returns at once when
+// the plan is not of its kind
 hipError_t launch_write(WsHeader* dhdr, const cl_tuning* t, uint32_t* edges, uint64_t lo, uint64_t hi,
-                        uint64_t* graph_offsets, uint32_t G, hipStream_t s) {
+                        uint64_t* graph_offsets, hipStream_t s) {
+  const uint32_t cus = std::max<uint32_t>(cus_of_current_device(), 1);
+  hipLaunchKernelGGL(k_compact, dim3(cus * 16), dim3(256), 0, s, dhdr, reinterpret_cast<uint2*>(edges), lo, hi);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
-  hipLaunchKernelGGL((k_lanes<true>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
+  hipLaunchKernelGGL((k_lanes<1>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
                      reinterpret_cast<uint2*>(edges), lo, hi);
-  (void)G;
   if (graph_offsets) hipLaunchKernelGGL(k_graph_offsets, dim3(16), dim3(256), 0, s, dhdr, graph_offsets);
   return hipGetLastError();
 }
@@ -344,27 +387,31 @@ cl_status cl_partition(const double* w, uint64_t n, double S, uint32_t P, void* 
 }
 
 // ----------------------------------------------------------- generation
-cl_status cl_workspace_size(const cl_graph* g, uint32_t G, const cl_tuning* t, uint64_t* fixed_bytes,
-                            uint64_t* estimate_bytes) {
+cl_status cl_workspace_size(const cl_graph* g, uint32_t G, const cl_tuning* t, uint32_t one_pass,
+                            uint64_t* fixed_bytes, uint64_t* estimate_bytes) {
   cl_status st = check_graphs(g, G);
   if (st != CL_OK) return st;
   const FixedLayout F = fixed_layout(g, G);
-  // estimate: lanes ~ (S/2 + 2 n_range) / budget per task, heavy segments ~ S / 512
+  // estimate (when S = sum w): expected edges <= S/2, plan cost ~ 16 (S/2 + 2 range),
+  // heavy segments ~ S/256
   const uint64_t bu = budget_units(t) / kCostUnit;
-  double nl = 0.0, nh = 0.0;
+  double nl = 0.0, nh = 0.0, cost = 0.0;
   for (uint32_t i = 0; i < G; ++i) {
     const double nr = static_cast<double>(g[i].u_end - g[i].u_begin);
     nl += (g[i].S * 0.5 + 2.0 * nr) / static_cast<double>(bu) + kLaneGroup;
     nh += g[i].S / 256.0 + 64.0;
+    cost += kCostUnit * (g[i].S * 0.5 + 2.0 * nr);
   }
-  const VarLayout V = var_layout(F.bytes, static_cast<uint64_t>(nh), static_cast<uint64_t>(nl) / kLaneGroup * kLaneGroup + kLaneGroup * G);
+  const uint64_t nl64 = static_cast<uint64_t>(nl) / kLaneGroup * kLaneGroup + kLaneGroup * G;
+  const VarLayout V = var_layout(F.bytes, static_cast<uint64_t>(nh), nl64, one_pass != 0,
+                                 one_pass ? slot_bound(static_cast<uint64_t>(cost), nl64) : 0);
   if (fixed_bytes) *fixed_bytes = F.bytes;
   if (estimate_bytes) *estimate_bytes = V.bytes;
   return CL_OK;
 }
 
-cl_status cl_count(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes, uint64_t* m_out,
-                   uint64_t* ws_required, void* stream) {
+static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes,
+                             uint64_t* m_out, uint64_t* ws_required, void* stream, uint32_t mode) {
   cl_status st = check_graphs(g, G);
   if (st != CL_OK) return st;
   if (!m_out) return CL_ERR_INVALID_ARG;
@@ -417,7 +464,9 @@ cl_status cl_count(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, 
   CL_TRY(hipStreamSynchronize(s));
   if (back.status) return status_error(back.status);
 
-  const VarLayout V = var_layout(F.bytes, back.total_nh, back.total_nl);
+  const bool one_pass = (mode == 1);
+  const VarLayout V = var_layout(F.bytes, back.total_nh, back.total_nl, one_pass,
+                                 one_pass ? slot_bound(back.total_cost, back.total_nl) : 0);
   if (ws_required) *ws_required = V.bytes;
   if (ws_bytes < V.bytes) return CL_ERR_WORKSPACE;
   h.cap_nh = back.total_nh;
@@ -431,19 +480,60 @@ cl_status cl_count(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, 
   h.lane_pos = reinterpret_cast<uint64_t*>(base + V.off_lpos);
   h.lane_scan_tmp = reinterpret_cast<uint64_t*>(base + V.off_lscan);
   h.group_graph = reinterpret_cast<uint32_t*>(base + V.off_groups);
+  h.mode = mode;
+  h.overflow = 0;
+  h.slot_margin = (t && t->slot_margin == 1) ? 1u : 0u;
+  if (one_pass) {
+    h.lane_cum = reinterpret_cast<uint64_t*>(base + V.off_lcum);
+    h.slot_off = reinterpret_cast<uint64_t*>(base + V.off_soff);
+    h.slot_scan_tmp = reinterpret_cast<uint64_t*>(base + V.off_sscan);
+    h.slots = reinterpret_cast<uint2*>(base + V.off_slots);
+    h.slot_cap = V.slot_cap;
+  } else {
+    h.lane_cum = nullptr;
+    h.slot_off = nullptr;
+    h.slot_scan_tmp = nullptr;
+    h.slots = nullptr;
+    h.slot_cap = 0;
+  }
   h.status = 0;
   h.queue = 0;
   h.planned = 0;
   CL_TRY(hipMemcpyAsync(dhdr, &h, sizeof(h), hipMemcpyHostToDevice, s));
-  CL_TRY(launch_plan_back(dhdr, h, t, s));
-  CL_TRY(hipMemcpyAsync(m_out, h.m_dev, 8ull * G, hipMemcpyDeviceToHost, s));
-  CL_TRY(hipMemcpyAsync(&back, dhdr, sizeof(back), hipMemcpyDeviceToHost, s));
-  CL_TRY(hipStreamSynchronize(s));
+  // the lane kernel is timed with HIP events on the caller's stream
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
+  if (ev0 && hipEventCreate(&ev1) != hipSuccess) {
+    (void)hipEventDestroy(ev0);
+    ev0 = nullptr;
+    ev1 = nullptr;
+  }
+  const hipError_t eb = launch_plan_back(dhdr, h, t, s, ev0, ev1);
+  float lane_ms = -1.0f;
+  if (eb == hipSuccess && hipMemcpyAsync(m_out, h.m_dev, 8ull * G, hipMemcpyDeviceToHost, s) == hipSuccess &&
+      hipMemcpyAsync(&back, dhdr, sizeof(back), hipMemcpyDeviceToHost, s) == hipSuccess &&
+      hipStreamSynchronize(s) == hipSuccess && ev0) {
+    if (hipEventElapsedTime(&lane_ms, ev0, ev1) != hipSuccess) lane_ms = -1.0f;
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (eb != hipSuccess) return CL_ERR_DEVICE;
   if (back.status) return status_error(back.status);
   const uint32_t one = 1;
+  CL_TRY(hipMemcpyAsync(&dhdr->lane_ms, &lane_ms, sizeof(lane_ms), hipMemcpyHostToDevice, s));
   CL_TRY(hipMemcpyAsync(&dhdr->planned, &one, sizeof(one), hipMemcpyHostToDevice, s));
   CL_TRY(hipStreamSynchronize(s));
   return CL_OK;
+}
+
+cl_status cl_count(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes, uint64_t* m_out,
+                   uint64_t* ws_required, void* stream) {
+  return plan_common(g, G, t, ws, ws_bytes, m_out, ws_required, stream, 0u);
+}
+
+cl_status cl_sample(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes, uint64_t* m_out,
+                    uint64_t* ws_required, void* stream) {
+  return plan_common(g, G, t, ws, ws_bytes, m_out, ws_required, stream, 1u);
 }
 
 cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t edge_begin, uint64_t cap,
@@ -453,12 +543,12 @@ cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t ed
   hipStream_t s = as_stream(stream);
   WsHeader* dhdr = static_cast<WsHeader*>(ws);
   // G for the offsets kernel: read from the header (the launch covers up to 2^20 tasks)
-  CL_TRY(launch_write(dhdr, t, edges, edge_begin, edge_begin + cap, graph_offsets, 1u << 20, s));
+  CL_TRY(launch_write(dhdr, t, edges, edge_begin, edge_begin + cap, graph_offsets, s));
   return CL_OK;
 }
 
 cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments, uint64_t* edges,
-                       uint64_t* candidates, void* stream) {
+                       uint64_t* candidates, float* lane_kernel_ms, uint32_t* overflow_lanes, void* stream) {
   if (!ws) return CL_ERR_INVALID_ARG;
   hipStream_t s = as_stream(stream);
   WsHeader back{};
@@ -469,6 +559,8 @@ cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments
   if (heavy_segments) *heavy_segments = back.total_nh;
   if (edges) *edges = back.total_m;
   if (candidates) *candidates = back.total_cand;
+  if (lane_kernel_ms) *lane_kernel_ms = back.lane_ms;
+  if (overflow_lanes) *overflow_lanes = back.overflow;
   if (back.status) return status_error(back.status);
   if (!back.planned) return CL_ERR_NOT_PLANNED;
   return CL_OK;
@@ -502,7 +594,7 @@ cl_status cl_batch_capture(const cl_graph* g, uint32_t G, const cl_tuning* t, vo
   CL_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   hipError_t e = launch_plan_front(dhdr, h, G, s);
   if (e == hipSuccess) e = launch_plan_back(dhdr, h, t, s);
-  if (e == hipSuccess) e = launch_write(dhdr, t, edges, 0, cap, graph_offsets, G, s);
+  if (e == hipSuccess) e = launch_write(dhdr, t, edges, 0, cap, graph_offsets, s);
   hipError_t e2 = hipStreamEndCapture(s, &graph);
   if (e != hipSuccess || e2 != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);

@@ -120,19 +120,12 @@ __device__ __forceinline__ double ln_unit(double x, const Series& sr) {
 }
 
 // ln(1 - p) for p in (0,1): for p < 1/4, -2 atanh(p/(2-p)) (no cancellation);
-// otherwise ln of the rounded 1 - p.  Both cases share one division and one
-// series: for small p the quotient is formed as (-p)/(2-p), which is exactly
-// the negated p/(2-p), so 2 s P(s^2) comes out with the sign of -2 atanh.
+// otherwise ln of the rounded 1 - p.  The small-p quotient is formed as
+// (-p)/(2-p), exactly the negated p/(2-p), so 2 s P(s^2) carries the sign of
+// -2 atanh without a separate negation.
 __device__ __forceinline__ double ln_one_minus(double p, const Series& sr) {
-  const bool small = p < 0.25;
-  double m;
-  int e;
-  log_reduce(1.0 - p, m, e);
-  const double f = m - 1.0;
-  const double num = small ? -p : f;
-  const double den = small ? (2.0 - p) : (2.0 + f);
-  const double l = two_s_series(num / den, sr);
-  return small ? l : ((static_cast<double>(e) * 0x1.62e42fefa39efp-1) + l);
+  if (p < 0.25) return two_s_series((-p) / (2.0 - p), sr);
+  return ln_unit(1.0 - p, sr);
 }
 
 __device__ __forceinline__ double cap1(double x) { return (x < 1.0) ? x : 1.0; }

@@ -304,10 +304,10 @@ struct NodeOut {
 __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
   GraphDesc* desc = hdr->desc;
   const uint32_t G = hdr->G;
-  uint64_t carry_nh = 0, carry_nl = 0;
+  uint64_t carry_nh = 0, carry_nl = 0, carry_cost = 0;
   for (uint32_t base = 0; base < G; base += blockDim.x) {
     const uint32_t g = base + threadIdx.x;
-    uint64_t nh = 0, nl = 0;
+    uint64_t nh = 0, nl = 0, cost = 0;
     if (g < G) {
       GraphDesc& d = desc[g];
       const uint64_t nr = d.u_end - d.u_begin;
@@ -323,12 +323,15 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
       }
       d.L = L;
       d.NH = nh;
+      cost = (L > 0) ? Z : 0;
       nl = (L + kLaneGroup - 1) / kLaneGroup * kLaneGroup;
       d.NL = nl;
     }
-    uint64_t tot_nh, tot_nl;
+    uint64_t tot_nh, tot_nl, tot_cost;
     const uint64_t ex_nh = block_exclusive<uint64_t>(nh, &tot_nh);
     const uint64_t ex_nl = block_exclusive<uint64_t>(nl, &tot_nl);
+    (void)block_exclusive<uint64_t>(cost, &tot_cost);
+    carry_cost += tot_cost;
     if (g < G) {
       desc[g].hs_off = carry_nh + ex_nh;
       desc[g].lane_off = carry_nl + ex_nl;
@@ -339,6 +342,7 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
   if (threadIdx.x == 0) {
     hdr->total_nh = carry_nh;
     hdr->total_nl = carry_nl;
+    hdr->total_cost = carry_cost;
     uint32_t st = 0;
     for (uint32_t g = 0; g < G; ++g) st |= desc[g].status;
     if (hdr->cap_nl != 0 && (carry_nh > hdr->cap_nh || carry_nl > hdr->cap_nl)) st |= kStCapacity;
@@ -404,7 +408,7 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
     const uint64_t r = i - d.r_off;
     const uint64_t nr = d.u_end - d.u_begin;
     if (r >= nr) continue;
-    hdr->A[i] = d.w[d.u_begin + r] / d.S;   // a_u of Alg. 1, once per source
+    hdr->A[i] = d.w[d.u_begin + r] / d.S;  // a_u of Alg. 1, once per source
     if (d.L == 0) continue;
     const uint64_t L = d.L;
     const uint64_t Z = d.C1 - d.C0;
@@ -422,6 +426,13 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
       if (kk > static_cast<double>(K - 1)) kk = static_cast<double>(K - 1);
       hdr->lane_start[d.lane_off + li] =
           make_uint2(static_cast<uint32_t>(d.u_begin + r), static_cast<uint32_t>(kk));
+      if (hdr->lane_cum) {
+        // plan cost before the lane's first segment (segments of a source share its cost equally)
+        const double before = static_cast<double>(cex) + kk * cnode / static_cast<double>(K);
+        uint64_t cb = static_cast<uint64_t>(before);
+        if (cb > cin) cb = cin;
+        hdr->lane_cum[d.lane_off + li] = cb;
+      }
     }
   }
 }
@@ -439,8 +450,10 @@ __global__ void __launch_bounds__(256) k_lane_groups(const WsHeader* hdr) {
     const GraphDesc& d = desc[g];
     hdr->group_graph[q] = g;
     for (uint64_t li = (l0 - d.lane_off); li < (l0 - d.lane_off) + kLaneGroup; ++li) {
-      if (li >= d.L)
+      if (li >= d.L) {
         hdr->lane_start[d.lane_off + li] = make_uint2(static_cast<uint32_t>(d.u_end), 0u);
+        if (hdr->lane_cum) hdr->lane_cum[d.lane_off + li] = d.C1 - d.C0;
+      }
     }
   }
 }
@@ -626,11 +639,29 @@ struct WriteEmit {
   }
 };
 
-template <bool kWrite>
+// One-pass output: the lane counts every kept edge and writes the first
+// `cap` of them into its slot (64-byte aligned), staged like WriteEmit.
+struct SlotEmit {
+  WriteEmit wr;      // window = the slot
+  uint32_t c;
+  __device__ bool operator()(uint32_t u, uint32_t v) {
+    ++c;
+    if (wr.pos < wr.hi) wr(u, v);
+    return true;
+  }
+};
+
+// kMode 0: count pass.  kMode 1: write pass (replay into the output window;
+// in one-pass plans only the lanes that overflowed their slot).  kMode 2:
+// one pass, count and write into slots.
+template <int kMode>
 __global__ void __launch_bounds__(256) k_lanes(WsHeader* hdr, uint2* out, uint64_t e_lo, uint64_t e_hi) {
+  constexpr bool kWrite = (kMode != 0);
   __shared__ uint2 stage[kWrite ? kStageSlots * 256 : 1];
   if (hdr->status || hdr->magic != kWsMagic) return;
-  if (kWrite && !hdr->planned) return;
+  if (kMode == 1 && !hdr->planned) return;
+  const bool only_overflow = (kMode == 1) && (uni32(hdr->mode) == 1);
+  if (only_overflow && uni32(hdr->overflow) == 0) return;
   const GraphDesc* desc = hdr->desc;
   const uint64_t ngroups = uni64(hdr->total_nl) / kLaneGroup;
   const Series sr = load_series();
@@ -665,10 +696,22 @@ __global__ void __launch_bounds__(256) k_lanes(WsHeader* hdr, uint2* out, uint64
     cx.SB0 = uni64(d.SB0);
     cx.hseg = to_global(uniptr(hdr->hseg) + uni64(d.hs_off));
     const RoundKeys rk = philox_round_keys(uni64(d.seed));
-    if (kWrite) {
+    if (kMode == 2) {
+      const uint64_t s0 = hdr->slot_off[l];
+      const uint64_t s1 = hdr->slot_off[l + 1];
+      // the writer indexes its window from the window start: out[i] is slot position s0 + i
+      SlotEmit em{WriteEmit{stage, threadIdx.x, blockDim.x, hdr->slots + s0, s0, s0, s1, s0}, 0u};
+      uint32_t visits = 0;
+      run_lane(cx, rk, sr, st.x, st.y, en.x, en.y, em, visits);
+      em.wr.finish();
+      hdr->lane_cnt[l] = em.c;
+      if (em.c > s1 - s0) atomicAdd(&hdr->overflow, 1u);
+      visited += visits;
+    } else if (kMode == 1) {
       const uint64_t pos0 = hdr->lane_pos[l];
       const uint64_t cnt = hdr->lane_cnt[l];
-      const bool touches = (pos0 < e_hi) && (pos0 + cnt > e_lo);
+      bool touches = (pos0 < e_hi) && (pos0 + cnt > e_lo);
+      if (only_overflow) touches = touches && (cnt > hdr->slot_off[l + 1] - hdr->slot_off[l]);
       if (__any(touches)) {
         WriteEmit em{stage, threadIdx.x, blockDim.x, out, pos0, e_lo, e_hi, pos0};
         uint32_t su = st.x, sk = st.y, eu = en.x, ek = en.y;
@@ -688,11 +731,72 @@ __global__ void __launch_bounds__(256) k_lanes(WsHeader* hdr, uint2* out, uint64
       visited += visits;
     }
   }
-  if (!kWrite) {
+  if (kMode != 1) {
     // candidates visited by the wavefront (statistics of the cost model)
     for (int dd = 32; dd >= 1; dd >>= 1) visited += shfl_idx64(visited, lane ^ dd);
     if (lane == 0)
       atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->total_cand), static_cast<unsigned long long>(visited));
+  }
+}
+
+// --------------------------------------------------------------------------
+// one-pass slots: capacity of a lane = its plan cost mu (in expected
+// candidates, which bounds its expected edges) + 8 sqrt(mu) + 24, rounded up
+// to whole 64-byte chunks; a lane above it (probability < 1e-14 by the
+// Chernoff bound used in Sec. 4, Theorem 2) is replayed by the write kernel.
+// --------------------------------------------------------------------------
+struct SlotIn {
+  const WsHeader* hdr;
+  uint64_t nl;
+  __device__ uint64_t load(uint64_t l) const {
+    if (l >= nl) return 0;
+    const GraphDesc& d = hdr->desc[hdr->group_graph[l / kLaneGroup]];
+    const uint64_t i = l - d.lane_off;
+    if (i >= d.L) return 0;
+    const uint64_t c1 = (i + 1 < d.L) ? hdr->lane_cum[l + 1] : (d.C1 - d.C0);
+    const uint64_t c0 = hdr->lane_cum[l];
+    const double mu = static_cast<double>(c1 > c0 ? c1 - c0 : 0) / static_cast<double>(kCostUnit);
+    const double cap = (hdr->slot_margin == 1) ? mu : (mu + 8.0 * sqrt(mu) + 24.0);
+    const uint64_t c = static_cast<uint64_t>(ceil(cap));
+    return (c + kStageSlots - 1) / kStageSlots * kStageSlots;
+  }
+};
+
+struct SlotOut {
+  uint64_t* off;
+  __device__ void store(uint64_t i, uint64_t, uint64_t ex) const { off[i] = ex; }
+};
+
+__global__ void k_slot_check(WsHeader* hdr) {
+  if (hdr->slot_off[hdr->total_nl] > hdr->slot_cap) atomicOr(&hdr->status, kStCapacity);
+}
+
+// copies every lane's slot to its place in the output window [lo, hi); one
+// wavefront per 64 lanes, 64 edges per step
+__global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out, uint64_t lo, uint64_t hi) {
+  if (hdr->status || hdr->mode != 1 || !hdr->planned) return;
+  const uint64_t ngroups = uni64(hdr->total_nl) / kLaneGroup;
+  const int lane = threadIdx.x & 63;
+  const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (blockDim.x / 64);
+  gptr<uint64_t> slots = to_global(uniptr(reinterpret_cast<const uint64_t*>(hdr->slots)));
+  uint64_t* out64 = reinterpret_cast<uint64_t*>(out);
+  for (uint64_t grp = uni64(static_cast<uint64_t>(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6));
+       grp < ngroups; grp += nwaves) {
+    const uint64_t l = grp * kLaneGroup + lane;
+    const uint64_t my_pos = hdr->lane_pos[l];
+    const uint64_t my_cnt = hdr->lane_cnt[l];
+    const uint64_t my_s0 = hdr->slot_off[l];
+    const uint64_t my_cap = hdr->slot_off[l + 1] - my_s0;
+    for (int j = 0; j < 64; ++j) {
+      const uint64_t pos = uni64(shfl_idx64(my_pos, j));
+      const uint64_t cnt = uni64(shfl_idx64(my_cnt, j));
+      const uint64_t s0 = uni64(shfl_idx64(my_s0, j));
+      const uint64_t cap = uni64(shfl_idx64(my_cap, j));
+      if (cnt == 0 || cnt > cap || pos >= hi || pos + cnt <= lo) continue;
+      const uint64_t a = (pos > lo) ? pos : lo;
+      const uint64_t b = (pos + cnt < hi) ? pos + cnt : hi;
+      for (uint64_t e = a + lane; e < b; e += 64) out64[e - lo] = slots[s0 + (e - pos)];
+    }
   }
 }
 

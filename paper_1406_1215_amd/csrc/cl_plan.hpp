@@ -72,6 +72,17 @@ struct WsHeader {
   uint64_t* lane_scan_tmp;
   uint64_t* m_dev;    // [G]
   uint32_t* group_graph; // [cap_nl / 64]
+  // one-pass mode: every lane writes into its own slot while it counts
+  uint64_t* lane_cum;    // [cap_nl + 1] cumulative plan cost at each lane's first segment
+  uint64_t* slot_off;    // [cap_nl + 1] exclusive prefix of the slot capacities (edges)
+  uint64_t* slot_scan_tmp;
+  uint2* slots;          // [slot_cap] edge pairs
+  uint64_t slot_cap;     // capacity of slots (edges)
+  uint32_t mode;         // 0: count then replay; 1: one pass into slots, then compaction
+  uint32_t overflow;     // lanes whose edges exceeded their slot (replayed by the write kernel)
+  uint32_t slot_margin;  // 0: mu + 8 sqrt(mu) + 24; 1: no margin
+  float lane_ms;         // duration of the last count / one-pass lane kernel (HIP events, ms)
+  uint64_t total_cost;   // sum of the graphs' plan costs (cost units)
   // device-written totals
   uint64_t total_nh, total_nl, total_m;
   uint64_t total_cand;  // candidates visited by the count pass

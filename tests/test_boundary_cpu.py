@@ -46,13 +46,13 @@ def test_host_side_argument_checks():
     g = (clgen.cl_graph * 1)(clgen.cl_graph(0, 10, 1.0, 1, 5, 3))
     fixed = ctypes.c_uint64(0)
     est = ctypes.c_uint64(0)
-    assert L.cl_workspace_size(g, 1, None, ctypes.byref(fixed), ctypes.byref(est)) == -1
+    assert L.cl_workspace_size(g, 1, None, 0, ctypes.byref(fixed), ctypes.byref(est)) == -1
     g = (clgen.cl_graph * 1)(clgen.cl_graph(0, 1 << 32, 1.0, 1, 0, 0))
-    assert L.cl_workspace_size(g, 1, None, ctypes.byref(fixed), ctypes.byref(est)) == -5
+    assert L.cl_workspace_size(g, 1, None, 0, ctypes.byref(fixed), ctypes.byref(est)) == -5
     g = (clgen.cl_graph * 1)(clgen.cl_graph(0, 0, -1.0, 1, 0, 0))
-    assert L.cl_workspace_size(g, 1, None, ctypes.byref(fixed), ctypes.byref(est)) == -1
+    assert L.cl_workspace_size(g, 1, None, 0, ctypes.byref(fixed), ctypes.byref(est)) == -1
     g = (clgen.cl_graph * 1)(clgen.cl_graph(0, 0, 1.0, 1, 0, 0))
-    assert L.cl_workspace_size(g, 1, None, ctypes.byref(fixed), ctypes.byref(est)) == 0
+    assert L.cl_workspace_size(g, 1, None, 0, ctypes.byref(fixed), ctypes.byref(est)) == 0
     assert est.value >= fixed.value > 0
     m = (ctypes.c_uint64 * 1)()
     req = ctypes.c_uint64(0)

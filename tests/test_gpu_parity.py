@@ -30,9 +30,12 @@ def _edges_np(t):
     return t.cpu().numpy().view(np.uint32).reshape(-1, 2)
 
 
-def _gpu_edges(cg, w, S, seed, u0=0, u1=None, tuning=None):
+PLANNERS = ["cl_count", "cl_sample"]
+
+
+def _gpu_edges(cg, w, S, seed, u0=0, u1=None, tuning=None, planner="cl_count"):
     wd = _to_dev(w)
-    plan = cg.cl_count([cg.Task(wd, S, seed, u0, u1)], tuning=tuning)
+    plan = getattr(cg, planner)([cg.Task(wd, S, seed, u0, u1)], tuning=tuning)
     e = cg.cl_generate(plan)
     return _edges_np(e)[: plan.total], plan
 
@@ -50,23 +53,25 @@ def test_weight_sum_is_exact(cg):
         assert cg.cl_weight_sum(wd) == O.exact_sum(w)
 
 
-def test_small_config_bit_exact(cg):
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_small_config_bit_exact(planner, cg):
     w = W.config_small()
     S = O.exact_sum(w)
     want, m, h, _ = O.generate(w, S, 1)
-    got, plan = _gpu_edges(cg, w, S, 1)
+    got, plan = _gpu_edges(cg, w, S, 1, planner=planner)
     assert plan.m == [m]
     assert np.array_equal(got, want)
 
 
 @pytest.mark.parametrize("seed", [1, 2, 12345678901234567])
-def test_edge_cases_bit_exact(cg, seed):
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_edge_cases_bit_exact(planner, cg, seed):
     for i, w in enumerate(W.tiny_cases(seed=40 + seed % 7, count=24)):
         if w.size == 0 or O.exact_sum(w) == 0.0:
             continue
         S = O.exact_sum(w)
         want, m, _, _ = O.generate(w, S, seed + i)
-        got, plan = _gpu_edges(cg, w, S, seed + i)
+        got, plan = _gpu_edges(cg, w, S, seed + i, planner=planner)
         assert plan.m == [m], (i, w.size)
         assert np.array_equal(got, want), (i, w.size)
 
@@ -90,13 +95,14 @@ def _heavy(n, seed, scale):
 
 
 @pytest.mark.parametrize("n,scale,seed", [(20000, 30.0, 1), (60000, 80.0, 2), (5000, 400.0, 3)])
-def test_segmented_sources_bit_exact(cg, n, scale, seed):
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_segmented_sources_bit_exact(planner, cg, n, scale, seed):
     w = _heavy(n, 50 + seed, scale)
     S = O.exact_sum(w)
     K0, _ = O.segments(w, S, 0)
     assert K0 > 1                      # the head is split into segments
     want, m, h, _ = O.generate(w, S, seed)
-    got, plan = _gpu_edges(cg, w, S, seed)
+    got, plan = _gpu_edges(cg, w, S, seed, planner=planner)
     info = cg.cl_plan_info(plan)
     assert info["heavy_segments"] > 0
     assert plan.m == [m]
@@ -104,26 +110,29 @@ def test_segmented_sources_bit_exact(cg, n, scale, seed):
 
 
 @pytest.mark.parametrize("u0,u1", [(0, 1), (0, 777), (500, 4000), (9999, 10000), (3000, 3000)])
-def test_source_ranges_bit_exact(cg, u0, u1):
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_source_ranges_bit_exact(planner, cg, u0, u1):
     w = W.config_small()
     S = O.exact_sum(w)
     want, m, _, _ = O.generate(w, S, 9, u0, u1)
-    got, plan = _gpu_edges(cg, w, S, 9, u0, u1)
+    got, plan = _gpu_edges(cg, w, S, 9, u0, u1, planner=planner)
     assert plan.m == [m]
     assert np.array_equal(got, want)
 
 
 @pytest.mark.parametrize("tuning", [{"lane_budget": 1}, {"lane_budget": 17}, {"lane_budget": 4096},
                                     {"lane_budget": 192, "blocks_per_cu": 1}, {"blocks_per_cu": 32}])
-def test_schedule_does_not_change_output(cg, tuning):
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_schedule_does_not_change_output(planner, cg, tuning):
     w = _heavy(30000, 60, 40.0)
     S = O.exact_sum(w)
     want, m, _, _ = O.generate(w, S, 4)
-    got, plan = _gpu_edges(cg, w, S, 4, tuning=tuning)
+    got, plan = _gpu_edges(cg, w, S, 4, tuning=tuning, planner=planner)
     assert np.array_equal(got, want)
 
 
-def test_batched_tasks_equal_single_tasks(cg):
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_batched_tasks_equal_single_tasks(planner, cg):
     import torch
     rng = np.random.default_rng(70)
     ws = [W.config_small(seed=int(rng.integers(1 << 30)), n=int(rng.integers(2, 3000))) for _ in range(7)]
@@ -134,7 +143,7 @@ def test_batched_tasks_equal_single_tasks(cg):
         e, m, _, _ = O.generate(w, S, 100 + i)
         wants.append(e)
         tasks.append(cg.Task(_to_dev(w), S, 100 + i))
-    plan = cg.cl_count(tasks)
+    plan = getattr(cg, planner)(tasks)
     assert plan.m == [x.shape[0] for x in wants]
     go = torch.zeros(len(tasks) + 1, dtype=torch.int64, device="cuda:0")
     e = _edges_np(cg.cl_generate(plan, graph_offsets=go))
@@ -144,12 +153,13 @@ def test_batched_tasks_equal_single_tasks(cg):
         assert np.array_equal(e[off[i]:off[i + 1]], want), i
 
 
-def test_write_windows(cg):
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_write_windows(planner, cg):
     import torch
     w = _heavy(40000, 80, 30.0)
     S = O.exact_sum(w)
     want, m, _, _ = O.generate(w, S, 6)
-    plan = cg.cl_count([cg.Task(_to_dev(w), S, 6)])
+    plan = getattr(cg, planner)([cg.Task(_to_dev(w), S, 6)])
     cuts = [0, 1, m // 3, m // 3 + 1, (2 * m) // 3, m]
     parts = []
     for a, b in zip(cuts[:-1], cuts[1:]):
@@ -202,7 +212,8 @@ def test_expected_edges_matches_oracle(cg):
         assert abs(V - Vo) <= 1e-9 * Vo
 
 
-def test_graph_capture_replays(cg):
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_graph_capture_replays(planner, cg):
     import torch
     rng = np.random.default_rng(95)
     ws = [W.config_small(seed=int(rng.integers(1 << 30)), n=int(rng.integers(100, 5000))) for _ in range(5)]
@@ -211,7 +222,7 @@ def test_graph_capture_replays(cg):
         S = O.exact_sum(w)
         wants.append(O.generate(w, S, 7 + i)[0])
         tasks.append(cg.Task(_to_dev(w), S, 7 + i))
-    plan = cg.cl_count(tasks)
+    plan = getattr(cg, planner)(tasks)
     s = torch.cuda.Stream()
     bg = cg.cl_batch_capture(plan, s)
     want_all = np.concatenate(wants)
@@ -229,17 +240,30 @@ def test_graph_capture_replays(cg):
     bg.close()
 
 
-def test_plain_config_full_size_digest(cg):
+_FULL = {}
+
+
+def _full_plain():
+    if not _FULL:
+        w = W.config_plain()
+        S = O.exact_sum(w)
+        _, m, h, _ = O.generate(w, S, 2, want_edges=False)
+        _FULL.update(w=w, S=S, m=m, h=h)
+    return _FULL
+
+
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_plain_config_full_size_digest(planner, cg):
     """n = 1e7 power law: count and digest equal the oracle's; invariants."""
     import torch
-    w = W.config_plain()
-    S = O.exact_sum(w)
+    F = _full_plain()
+    w, S = F["w"], F["S"]
     wd = _to_dev(w)
     assert cg.cl_weight_sum(wd) == S
-    plan = cg.cl_count([cg.Task(wd, S, 2)])
+    plan = getattr(cg, planner)([cg.Task(wd, S, 2)])
     e = cg.cl_generate(plan)
     acc = cg.cl_hash_edges(e)
-    _, m, h, _ = O.generate(w, S, 2, want_edges=False)
+    m, h = F["m"], F["h"]
     assert plan.m == [m]
     assert cg.hash_value(acc) == h
     # sampled windows compared edge by edge with single-source oracle runs
@@ -255,16 +279,29 @@ def test_plain_config_full_size_digest(cg):
 
 
 @pytest.mark.parametrize("n", [100_000, 1_000_000])
-def test_plain_shapes_bit_exact(cg, n):
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_plain_shapes_bit_exact(planner, cg, n):
     """Smaller instances of the n = 1e7 shape (many capped sources at the head);
     n = 1e5 is the input on which an earlier persistent-loop miscompilation
     (single-lane tail merged into the loop head) never terminated."""
     w = W.config_plain(n=n)
     S = O.exact_sum(w)
     want, m, _, _ = O.generate(w, S, 2)
-    got, plan = _gpu_edges(cg, w, S, 2)
+    got, plan = _gpu_edges(cg, w, S, 2, planner=planner)
     assert plan.m == [m]
     assert np.array_equal(got, want)
     info = cg.cl_plan_info(plan)
     _, _, _, cand = O.generate(w, S, 2, want_edges=False)
     assert info["candidates"] == cand
+
+
+@pytest.mark.parametrize("tuning", [{"slot_margin": 1}, {"slot_margin": 1, "lane_budget": 7}])
+def test_one_pass_slot_overflow_replay(cg, tuning):
+    """Slots without a margin: about half the lanes overflow and are replayed
+    by the write kernel; the output is unchanged."""
+    w = _heavy(30000, 61, 40.0)
+    S = O.exact_sum(w)
+    want, m, _, _ = O.generate(w, S, 5)
+    got, plan = _gpu_edges(cg, w, S, 5, tuning=tuning, planner="cl_sample")
+    assert plan.m == [m]
+    assert np.array_equal(got, want)
