@@ -95,6 +95,8 @@ def lib():
     L.orc_graph_codes.argtypes = [_f64p, ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                   ctypes.c_double, _u64p]
     L.orc_graph_codes.restype = ctypes.c_int
+    L.orc_exact_sum.argtypes = [_f64p, ctypes.c_uint64, _f64p]
+    L.orc_exact_sum.restype = ctypes.c_int
     _LIB = L
     return L
 
@@ -142,8 +144,21 @@ def mix64(x):
 # ------------------------------------------------------------- exact sum S
 def exact_sum(w) -> float:
     """S of Alg. 1, correctly rounded: the exact real sum of the weights
-    rounded once to the nearest double (``math.fsum``)."""
-    return math.fsum(np.asarray(w, dtype=np.float64).tolist())
+    rounded once to the nearest double (``math.fsum`` for up to a million
+    weights, the C accumulation of the same algorithm beyond)."""
+    w = np.asarray(w, dtype=np.float64)
+    if w.size <= 1_000_000:
+        return math.fsum(w.tolist())
+    return exact_sum_c(w)
+
+
+def exact_sum_c(w) -> float:
+    w, wp = _f64(w)
+    out = ctypes.c_double(0.0)
+    st = lib().orc_exact_sum(wp, w.size, ctypes.byref(out))
+    if st != 0:
+        raise OracleError(st)
+    return out.value
 
 
 def validate(w, S) -> int:

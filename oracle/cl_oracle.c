@@ -599,3 +599,63 @@ int orc_graph_codes(const double* w, uint64_t n, double S, uint64_t seed0, uint6
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* S of Alg. 1 for large inputs: the exact sum rounded once to nearest, by   */
+/* Shewchuk's error-free accumulation ("Adaptive precision floating-point   */
+/* arithmetic", 1997): a list of non-overlapping partials is kept exact with */
+/* two-sum; the partials are then added from the largest, with the final    */
+/* half-way correction that makes the result correctly rounded.  Returns    */
+/* 0 on success, -4 if an intermediate overflows.                            */
+/* ------------------------------------------------------------------------ */
+int orc_exact_sum(const double* x, uint64_t n, double* out)
+{
+    size_t cap = 64, np = 0;
+    double* p = (double*)malloc(cap * sizeof(double));
+    if (!p) return ORC_ERR_INVALID_ARG;
+    for (uint64_t i = 0; i < n; ++i) {
+        double v = x[i];
+        size_t k = 0;
+        for (size_t j = 0; j < np; ++j) {
+            double y = p[j];
+            double a = (fabs(v) < fabs(y)) ? y : v;
+            double b = (fabs(v) < fabs(y)) ? v : y;
+            double hi = a + b;
+            double lo = b - (hi - a);
+            if (lo != 0.0) p[k++] = lo;
+            v = hi;
+        }
+        if (v - v != 0.0) { free(p); return ORC_ERR_NONFINITE; }   /* inf: the sum overflowed */
+        np = k;
+        if (np + 1 > cap) {
+            cap *= 2;
+            double* q = (double*)realloc(p, cap * sizeof(double));
+            if (!q) { free(p); return ORC_ERR_INVALID_ARG; }
+            p = q;
+        }
+        p[np++] = v;
+    }
+    /* sum the partials from the top; stop at the first inexact addition */
+    double hi = 0.0, lo = 0.0;
+    size_t j = np;
+    if (j > 0) {
+        hi = p[--j];
+        while (j > 0) {
+            double y = p[--j];
+            double s = hi + y;
+            lo = y - (s - hi);
+            hi = s;
+            if (lo != 0.0) break;
+        }
+        /* half-way case: if the remaining partials push past the tie, round
+           the other way (the neighbouring partial has the same sign as lo) */
+        if (j > 0 && ((lo < 0.0 && p[j - 1] < 0.0) || (lo > 0.0 && p[j - 1] > 0.0))) {
+            double y = lo * 2.0;
+            double s = hi + y;
+            if (y == s - hi) hi = s;
+        }
+    }
+    free(p);
+    *out = hi;
+    return ORC_OK;
+}

@@ -1,0 +1,105 @@
+"""Autotuner of the generator's schedule knobs.
+
+The knobs (cl_tuning: lane budget = expected candidates per lane, i.e. the
+chunk size of the uniform-cost split of Eq. 5 across lanes, and the
+persistent grid in blocks per compute unit) change only the launch schedule:
+the edge list is a pure function of (w, S, seed, range).  The tuner times
+every candidate setting on the caller's tasks, checks that each produces the
+same digest as the first, and keeps the fastest.  Results are cached per
+(device, size bucket) in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from typing import Dict, Iterable, List, Optional, Sequence
+
+import torch
+
+from . import clgen
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+BUDGETS = (64, 96, 128, 192, 256, 384, 512)
+BLOCKS_PER_CU = (4, 8, 16)
+
+
+def size_bucket(total_edges: float) -> str:
+    """log2 bucket of the expected output size."""
+    return f"e2^{int(math.floor(math.log2(max(total_edges, 1.0))))}"
+
+
+def device_key() -> str:
+    p = torch.cuda.get_device_properties(0)
+    return f"{p.name}:{getattr(p, 'gcnArchName', '')}:{p.multi_processor_count}"
+
+
+def _run(tasks, tuning, planner, edges=None):
+    plan = getattr(clgen, planner)(tasks, tuning=tuning)
+    m = plan.total
+    if edges is None or edges.shape[0] < m:
+        edges = torch.empty((max(m, 1) + 1024, 2), dtype=torch.int32, device=tasks[0].w.device)
+    clgen.cl_generate(plan, edges=edges, cap=m)
+    return plan, edges
+
+
+def tune(tasks: Sequence[clgen.Task], planner: str = "cl_sample", budgets: Iterable[int] = BUDGETS,
+         blocks: Iterable[int] = BLOCKS_PER_CU, reps: int = 2, save: bool = True) -> Dict:
+    """Times every (budget, blocks_per_cu) pair; returns the fastest and the
+    table.  Raises if any setting changes the output digest."""
+    tasks = list(tasks)
+    table = []
+    ref_hash = None
+    edges = None
+    for b in budgets:
+        for bpc in blocks:
+            tun = {"lane_budget": int(b), "blocks_per_cu": int(bpc)}
+            plan, edges = _run(tasks, tun, planner, edges)           # warm (and sizes the workspace)
+            m = plan.total
+            acc = clgen.cl_hash_edges(edges[:m])
+            h = clgen.hash_value(acc)
+            if ref_hash is None:
+                ref_hash = (m, h)
+            elif (m, h) != ref_hash:
+                raise RuntimeError(f"tuning {tun} changed the output ({(m, h)} != {ref_hash})")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan, edges = _run(tasks, tun, planner, edges)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            table.append({"lane_budget": int(b), "blocks_per_cu": int(bpc), "ms": dt * 1e3})
+    best = min(table, key=lambda r: r["ms"])
+    result = {"best": {"lane_budget": best["lane_budget"], "blocks_per_cu": best["blocks_per_cu"]},
+              "best_ms": best["ms"], "table": table, "edges": ref_hash[0]}
+    if save:
+        store(size_bucket(ref_hash[0]), result["best"], best["ms"])
+    return result
+
+
+def load() -> Dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def store(bucket: str, best: Dict, ms: float) -> None:
+    data = load()
+    data.setdefault(device_key(), {})[bucket] = {"tuning": best, "ms": ms}
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def lookup(expected_edges: float) -> Optional[Dict]:
+    """Cached tuning for a task of about this many edges (nearest bucket)."""
+    data = load().get(device_key() if torch.cuda.is_available() else "", {})
+    if not data:
+        return None
+    want = int(math.floor(math.log2(max(expected_edges, 1.0))))
+    best = min(data.items(), key=lambda kv: abs(int(kv[0].split("^")[1]) - want))
+    return dict(best[1]["tuning"])

@@ -211,11 +211,14 @@ def _plan(fn_name: str, one_pass: int, tasks: Sequence[Task], tuning, ws, stream
     tun = _tuning(tuning)
     dev = tasks[0].w.device
     if ws is None:
+        # the part known before the data is seen; the data-dependent rest is
+        # reported by the first call (CL_ERR_WORKSPACE + required bytes)
         fixed = _U64(0)
         est = _U64(0)
         _check(L.cl_workspace_size(arr, G, tun, one_pass, ctypes.byref(fixed), ctypes.byref(est)),
                "cl_workspace_size")
-        ws = _ws(est.value, dev)
+        free = torch.cuda.mem_get_info(dev)[0]
+        ws = _ws(est.value if est.value < free // 4 else fixed.value, dev)
     m = (ctypes.c_uint64 * G)()
     req = _U64(0)
     fn = getattr(L, fn_name)

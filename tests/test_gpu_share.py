@@ -1,0 +1,101 @@
+"""GPU, full size: one GPU's share of the paper's largest PL shape.
+
+n = 1e9 weights (exponent 2.1, mean 500, cap sqrt(500 n)), S exact, the
+uniform consecutive partition into 64 parts (Eq. 5) equal to the oracle's,
+then part 0 (the heavy head, ~3.9e9 edges) generated in one pass and written
+out in 4 slabs.  Checked: partition bounds bit-exact; per-source edge lists
+bit-exact on sampled sources; sortedness / u < v / range across all slabs;
+digest identical between the one-pass and the count-then-replay paths."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1406_1215_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def cg():
+    from conftest import gpu_available
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    if free < 120 * (1 << 30):
+        pytest.skip("needs ~120 GiB of device memory")
+    from paper_1406_1215_amd import clgen
+    clgen.lib()
+    return clgen
+
+
+def test_share_of_the_billion_node_graph(cg):
+    import torch
+    print("share: generating 1e9 weights", flush=True)
+    w = W.config_share()
+    n = w.size
+    assert abs(w.mean() - 500.0) < 5.0
+    wd = torch.from_numpy(w).to("cuda:0")
+    S = cg.cl_weight_sum(wd)
+    print("share: oracle exact sum", flush=True)
+    assert S == O.exact_sum(w)
+    P = 64
+    bounds, Z = cg.cl_partition(wd, S, P)
+    print("share: oracle partition", flush=True)
+    ob, oZ = O.partition(w, S, P)
+    assert Z == oZ and bounds == [int(x) for x in ob]
+    u1 = bounds[1]
+    seed = 3
+    # one pass into slots, then 4 slabs through one buffer
+    plan = cg.cl_sample([cg.Task(wd, S, seed, 0, u1)])
+    m = plan.total
+    info = cg.cl_plan_info(plan)
+    print(f"share: part 0 = sources [0, {u1}), {m} edges, {info['lanes']} lanes, "
+          f"one pass {info['lane_kernel_ms']:.1f} ms", flush=True)
+    # Theorem 2: the part's edge count is within 3/2 of its expectation; the
+    # cost model puts ~Z/P into each part
+    assert 0.5 * Z / P / 256 < m < 1.5 * Z / P / 256
+    slab = (m + 3) // 4
+    buf = torch.empty((slab + 8, 2), dtype=torch.int32, device="cuda:0")
+    acc1 = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    last_key = -1
+    rng = np.random.default_rng(5)
+    picks = sorted(set([0, 1, 2, u1 - 1] + list(rng.integers(0, u1, 8))))
+    qs, Q = O.qscan(w)
+    found = {}
+    for s in range(4):
+        b0 = s * slab
+        c = min(slab, m - b0)
+        e = cg.cl_generate(plan, edges=buf, edge_begin=b0, cap=c)[:c]
+        cg.cl_hash_edges(e, b0, acc1)
+        u = e[:, 0].to(torch.int64) & 0xFFFFFFFF
+        v = e[:, 1].to(torch.int64) & 0xFFFFFFFF
+        assert bool((u < v).all()) and bool((u < u1).all()) and bool((v < n).all())
+        key = u * (1 << 32) + v
+        assert bool((key[1:] > key[:-1]).all())
+        assert int(key[0]) > last_key
+        last_key = int(key[-1])
+        for src in picks:
+            lo = int(torch.searchsorted(u, torch.tensor([src], device="cuda:0"), right=False))
+            hi = int(torch.searchsorted(u, torch.tensor([src], device="cuda:0"), right=True))
+            if hi > lo:
+                found.setdefault(src, []).append(v[lo:hi].cpu().numpy())
+        print(f"share: slab {s} checked", flush=True)
+    for src in picks:
+        want = O.node_edges(w, S, seed, src, Q=Q, qscale=qs)
+        got = np.concatenate(found.get(src, [np.zeros(0, dtype=np.int64)])).astype(np.uint32)
+        assert np.array_equal(got, want), src
+    del plan
+    torch.cuda.empty_cache()
+    # the count-then-replay path gives the same digest
+    plan2 = cg.cl_count([cg.Task(wd, S, seed, 0, u1)])
+    assert plan2.total == m
+    acc2 = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    for s in range(4):
+        b0 = s * slab
+        c = min(slab, m - b0)
+        e = cg.cl_generate(plan2, edges=buf, edge_begin=b0, cap=c)[:c]
+        cg.cl_hash_edges(e, b0, acc2)
+    assert cg.hash_value(acc1) == cg.hash_value(acc2)

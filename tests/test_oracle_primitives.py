@@ -212,3 +212,23 @@ def test_mix64_known_values():
     # splitmix64 (Steele, Lea, Flood, OOPSLA 2014): state 0 -> first output of the
     # generator seeded with 0 is mix(0 + golden) = 0xE220A8397B1DCDAF
     assert O.mix64(0) == 0xE220A8397B1DCDAF
+
+
+def test_exact_sum_c_matches_fsum_and_fractions():
+    from fractions import Fraction
+    rng = np.random.default_rng(8)
+    for trial in range(40):
+        kind = trial % 4
+        if kind == 0:
+            w = rng.pareto(1.1, 3000) * 10 ** rng.uniform(-8, 8)
+        elif kind == 1:
+            w = np.concatenate([rng.random(2000), [1e16, 3.0, 2.0 ** -60], rng.random(10) * 1e-300])
+        elif kind == 2:
+            # ties to even at the last bit: 2^53 + 1 + tiny terms
+            w = np.array([2.0 ** 53, 1.0, 2.0 ** -40, 2.0 ** -41] + list(rng.random(50) * 2.0 ** -45))
+        else:
+            w = np.sort(rng.pareto(0.6, 5000))[::-1] * 3.7
+        rng.shuffle(w)
+        want = float(sum(Fraction(float(x)) for x in w))
+        assert O.exact_sum_c(w) == want
+        assert O.exact_sum_c(w) == math.fsum(w.tolist())
