@@ -54,9 +54,10 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
-    L = ctypes.CDLL(LIB_PATH)
+    path = os.environ.get("CLGEN_LIBRARY", LIB_PATH)   # another build of the same library
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(path)
     S = ctypes.c_int32
     sig = {
         "cl_weight_sum_workspace": (S, [_U64, _U64P]),

@@ -25,6 +25,7 @@ constexpr uint64_t kAlign = 256;
 constexpr uint32_t kDefaultBudget = 192;
 constexpr uint32_t kDefaultBlocksPerCu = 8;
 constexpr int kPersistThreads = 256;
+static_assert(kPersistThreads == kLaneThreads, "the lane kernels stage output for 256 threads");
 
 inline uint64_t align_up(uint64_t x, uint64_t a = kAlign) { return (x + a - 1) / a * a; }
 
@@ -116,9 +117,9 @@ VarLayout var_layout(uint64_t base, uint64_t nh, uint64_t nl, bool one_pass, uin
   VarLayout V{};
   uint64_t off = align_up(base);
   V.off_hseg = off;
-  off = align_up(off + 4 * std::max<uint64_t>(nh, 1));
+  off = align_up(off + sizeof(HSeg) * std::max<uint64_t>(nh, 1));
   V.off_lstart = off;
-  off = align_up(off + 8 * std::max<uint64_t>(nl, 1));
+  off = align_up(off + 4 * std::max<uint64_t>(nl, 1));
   V.off_lcnt = off;
   off = align_up(off + 4 * std::max<uint64_t>(nl, 1));
   V.off_lpos = off;
@@ -199,7 +200,7 @@ hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* 
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
   if (h.mode == 1) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->overflow, 0u);
-    hipError_t e = device_scan<uint64_t>(SlotIn{dhdr, h.cap_nl}, SlotOut{h.slot_off}, h.cap_nl + 1,
+    hipError_t e = device_scan<uint64_t>(SlotIn{dhdr}, SlotOut{{}, h.slot_off}, h.cap_nl + 1,
                                          h.slot_scan_tmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_slot_check, dim3(1), dim3(1), 0, s, dhdr);
@@ -213,7 +214,7 @@ hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* 
                        static_cast<uint2*>(nullptr), 0ull, 0ull);
     if (ev1) (void)hipEventRecord(ev1, s);
   }
-  hipError_t e = device_scan<uint64_t>(CntIn{h.lane_cnt, h.cap_nl}, OffOut{h.lane_pos}, h.cap_nl + 1,
+  hipError_t e = device_scan<uint64_t>(CntIn{{}, h.lane_cnt, h.cap_nl}, OffOut{{}, h.lane_pos}, h.cap_nl + 1,
                                        h.lane_scan_tmp, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_graph_edges, dim3(grid_for(h.G, 256, cap)), dim3(256), 0, s, dhdr, h.m_dev);
@@ -315,7 +316,7 @@ cl_status cl_expected_edges(const double* w, uint64_t n, double S, void* ws, uin
   Dbl2* scan_tmp = reinterpret_cast<Dbl2*>(base + align_up(16 * (n + 1)));
   Dbl2* parts = reinterpret_cast<Dbl2*>(base + align_up(16 * (n + 1)) + align_up(16 * (nt + 8)));
   Dbl2* out = reinterpret_cast<Dbl2*>(base + align_up(16 * (n + 1)) + align_up(16 * (nt + 8)) + align_up(16 * 4096));
-  CL_TRY((device_scan<Dbl2>(SufIn{w, n}, SufOut{suf, n}, n + 1, scan_tmp, s)));
+  CL_TRY((device_scan<Dbl2>(SufIn{{}, w, n}, SufOut{{}, suf, n}, n + 1, scan_tmp, s)));
   const uint32_t nb = grid_for(n, 256, 4096);
   hipLaunchKernelGGL(k_expected_edges, dim3(nb), dim3(256), 0, s, w, n, S, suf, parts);
   hipLaunchKernelGGL(k_reduce_dbl2, dim3(1), dim3(256), 0, s, parts, nb, out);
@@ -371,7 +372,7 @@ cl_status cl_partition(const double* w, uint64_t n, double S, uint32_t P, void* 
   hipLaunchKernelGGL((k_validate<false>), dim3(grid_for(n + 1, 256, cap)), dim3(256), 0, s, d, 1u, n + 1,
                      static_cast<unsigned long long*>(nullptr));
   CL_TRY((device_scan<uint64_t>(QIn{d, 1u}, QOut{d, 1u, Q}, n + 1, tmp, s)));
-  CL_TRY((device_scan<uint64_t>(PartIn{d, Q}, PartOut{C}, n + 1, tmp, s)));
+  CL_TRY((device_scan<uint64_t>(PartIn{{}, d, Q}, PartOut{{}, C}, n + 1, tmp, s)));
   hipLaunchKernelGGL(k_part_bounds, dim3(grid_for(static_cast<uint64_t>(P) + 1, 256, 1024)), dim3(256), 0, s, C, n,
                      P, bd);
   CL_TRY(hipGetLastError());
@@ -474,8 +475,8 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
   h.total_nh = back.total_nh;
   h.total_nl = back.total_nl;
   h.bytes_total = V.bytes;
-  h.hseg = reinterpret_cast<uint32_t*>(base + V.off_hseg);
-  h.lane_start = reinterpret_cast<uint2*>(base + V.off_lstart);
+  h.hseg = reinterpret_cast<HSeg*>(base + V.off_hseg);
+  h.lane_seg = reinterpret_cast<uint32_t*>(base + V.off_lstart);
   h.lane_cnt = reinterpret_cast<uint32_t*>(base + V.off_lcnt);
   h.lane_pos = reinterpret_cast<uint64_t*>(base + V.off_lpos);
   h.lane_scan_tmp = reinterpret_cast<uint64_t*>(base + V.off_lscan);

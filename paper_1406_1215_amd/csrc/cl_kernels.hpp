@@ -126,73 +126,92 @@ __global__ void __launch_bounds__(256) k_validate(GraphDesc* desc, uint32_t G, u
 }
 
 // Rounds sum_b (hi_b 2^32 + lo_b) 2^(b-1) * 2^-1074 to the nearest double
-// (ties to even).  One thread.  35 limbs of 64 bits cover 2^2240.
+// (ties to even).  One wavefront: lane L owns limb L (bits [64 L, 64 L + 64))
+// of the big integer T; 36 limbs cover 2^2304.  Zero bins are skipped.
 constexpr int kLimbs = 36;
 
-__global__ void k_sum_finalize(const unsigned long long* bins, double* S_out, uint32_t* status) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  uint64_t T[kLimbs];
-  for (int i = 0; i < kLimbs; ++i) T[i] = 0;
-  auto add_shifted = [&](uint64_t val, int sh) {
-    // T += val << sh
-    if (!val) return;
-    int li = sh >> 6;
+__global__ void __launch_bounds__(64) k_sum_finalize(const unsigned long long* bins, double* S_out,
+                                                     uint32_t* status) {
+  if (blockIdx.x != 0) return;
+  const int L = threadIdx.x;   // limb
+  uint64_t acc = 0, carry = 0;  // limb value acc + carry 2^64
+  auto add_at = [&](uint64_t val, int sh) {
+    const int li = sh >> 6;
     const int bs = sh & 63;
-    uint64_t lo = val << bs;
-    uint64_t hi = bs ? (val >> (64 - bs)) : 0;
-    uint64_t old = T[li];
-    T[li] = old + lo;
-    uint64_t carry = (T[li] < old) ? 1 : 0;
-    ++li;
-    uint64_t add = hi + carry;           // hi < 2^63, no overflow
-    while (add && li < kLimbs) {
-      old = T[li];
-      T[li] = old + add;
-      add = (T[li] < old) ? 1 : 0;
-      ++li;
-    }
+    uint64_t part = 0;
+    if (L == li) part = val << bs;
+    if (L == li + 1 && bs != 0) part = val >> (64 - bs);
+    acc += part;
+    carry += (acc < part) ? 1 : 0;
   };
-  for (int b = 1; b < kBins; ++b) {
-    add_shifted(bins[2 * b], b - 1);
-    add_shifted(bins[2 * b + 1], b - 1 + 32);
-  }
-  int top = -1;
-  for (int li = kLimbs - 1; li >= 0; --li) {
-    if (T[li]) {
-      top = li * 64 + 63 - __clzll(static_cast<long long>(T[li]));
-      break;
+  for (int b0 = 0; b0 < 2 * kBins; b0 += 64) {
+    const uint64_t mine = bins[b0 + L];
+    uint64_t nz = __ballot(mine != 0);
+    while (nz) {
+      const int k = __ffsll(static_cast<long long>(nz)) - 1;
+      nz &= nz - 1;
+      const int idx = b0 + k;                // bin b = idx / 2, half idx & 1
+      const int b = idx >> 1;
+      if (b == 0) continue;                  // bin 0 is never filled
+      add_at(shfl_idx64(mine, k), (b - 1) + ((idx & 1) ? 32 : 0));
     }
   }
-  auto bit_at = [&](int p) -> uint64_t { return (T[p >> 6] >> (p & 63)) & 1ull; };
+  // carry propagation, limb by limb
+  uint64_t T = 0, cin = 0;
+  for (int l = 0; l < kLimbs; ++l) {
+    const uint64_t a = shfl_idx64(acc, l);
+    const uint64_t c = shfl_idx64(carry, l);
+    const uint64_t t = a + cin;
+    if (L == l) T = t;
+    cin = c + ((t < cin) ? 1 : 0);
+  }
+  auto limb = [&](int l) -> uint64_t { return (l >= 0 && l < kLimbs) ? shfl_idx64(T, l) : 0ull; };
+  const uint64_t nzl = __ballot(L < kLimbs && T != 0);
   double S;
-  if (top < 0) {
+  if (nzl == 0) {
     S = 0.0;
-  } else if (top <= 52) {
-    S = __longlong_as_double(static_cast<long long>(T[0]));   // value = T * 2^-1074, bits = T
   } else {
-    const int shift = top - 52;
-    uint64_t mant = 0;
-    for (int p = top; p >= shift; --p) mant = (mant << 1) | bit_at(p);
-    const uint64_t half = bit_at(shift - 1);
-    bool sticky = false;
-    for (int p = shift - 2; p >= 0 && !sticky; --p) sticky = bit_at(p) != 0;
-    int e = shift + 1;
-    if (half && (sticky || (mant & 1ull))) {
-      ++mant;
-      if (mant == (1ull << 53)) {
-        mant >>= 1;
-        ++e;
+    const int topL = 63 - __clzll(static_cast<long long>(nzl));
+    const uint64_t tv = limb(topL);
+    const int top = topL * 64 + 63 - __clzll(static_cast<long long>(tv));
+    if (top <= 52) {
+      S = __longlong_as_double(static_cast<long long>(limb(0)));   // value = T 2^-1074, bits = T
+    } else {
+      const int shift = top - 52;   // mant = bits [shift, top]
+      auto bits_from = [&](int p) -> uint64_t {
+        // 64 bits of T starting at bit p (p >= 0)
+        const int l = p >> 6, o = p & 63;
+        const uint64_t lo = limb(l), hi = limb(l + 1);
+        return o ? ((lo >> o) | (hi << (64 - o))) : lo;
+      };
+      uint64_t mant = bits_from(shift) & ((1ull << 53) - 1);
+      const int hp = shift - 1;    // half bit
+      const uint64_t half = (bits_from(hp) & 1ull);
+      bool sticky = false;
+      if (hp > 0) {
+        const int ls = hp >> 6, os = hp & 63;
+        sticky = (os != 0) && ((limb(ls) & ((1ull << os) - 1)) != 0);
+        const uint64_t below = (ls > 0) ? (nzl & ((1ull << ls) - 1)) : 0ull;
+        sticky = sticky || (below != 0);
+      }
+      int e = shift + 1;
+      if (half && (sticky || (mant & 1ull))) {
+        ++mant;
+        if (mant == (1ull << 53)) {
+          mant >>= 1;
+          ++e;
+        }
+      }
+      if (e >= 2047) {
+        S = __longlong_as_double(0x7FF0000000000000ll);
+        if (L == 0) atomicOr(status, kStNonfinite);
+      } else {
+        S = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(e) << 52) |
+                                                        (mant & 0x000FFFFFFFFFFFFFull)));
       }
     }
-    if (e >= 2047) {
-      S = __longlong_as_double(0x7FF0000000000000ll);
-      atomicOr(status, kStNonfinite);
-    } else {
-      S = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(e) << 52) |
-                                                      (mant & 0x000FFFFFFFFFFFFFull)));
-    }
   }
-  *S_out = S;
+  if (L == 0) *S_out = S;
 }
 
 // status words are cleared at the start of every plan (a replayed graph
@@ -219,12 +238,22 @@ __global__ void k_graph_init(GraphDesc* desc, uint32_t G) {
 struct QIn {
   const GraphDesc* desc;
   uint32_t G;
-  __device__ uint64_t load(uint64_t i) const {
-    const uint32_t g = find_graph(G, i, [&](uint32_t x) { return desc[x].q_off; });
+  struct Ctx {
+    const double* w;
+    uint64_t n, q_off;
+    double qscale;
+  };
+  __device__ uint32_t graph_of(uint64_t i) const {
+    return find_graph(G, i, [&](uint32_t x) { return desc[x].q_off; });
+  }
+  __device__ Ctx context(uint32_t g) const {
     const GraphDesc& d = desc[g];
-    const uint64_t v = i - d.q_off;
-    if (v >= d.n || d.qscale == 0.0) return 0;
-    return quantise(d.w[v], d.qscale);
+    return Ctx{d.w, d.n, d.q_off, d.qscale};
+  }
+  __device__ uint64_t load(uint64_t i, const Ctx& c) const {
+    const uint64_t v = i - c.q_off;
+    if (v >= c.n || c.qscale == 0.0) return 0;
+    return quantise(c.w[v], c.qscale);
   }
 };
 
@@ -232,13 +261,16 @@ struct QOut {
   GraphDesc* desc;
   uint32_t G;
   uint64_t* Q;
-  __device__ void store(uint64_t i, uint64_t, uint64_t ex) const {
+  struct Ctx {
+    GraphDesc* d;
+    uint64_t n, q_off;
+  };
+  __device__ Ctx context(uint32_t g) const { return Ctx{desc + g, desc[g].n, desc[g].q_off}; }
+  __device__ void store(uint64_t i, const Ctx& c, uint64_t, uint64_t ex) const {
     Q[i] = ex;
-    const uint32_t g = find_graph(G, i, [&](uint32_t x) { return desc[x].q_off; });
-    GraphDesc& d = desc[g];
-    const uint64_t v = i - d.q_off;
-    if (v == 0) d.Qbase = ex;
-    if (v == d.n) d.Qend = ex;
+    const uint64_t v = i - c.q_off;
+    if (v == 0) c.d->Qbase = ex;
+    if (v == c.n) c.d->Qend = ex;
   }
 };
 
@@ -251,26 +283,36 @@ struct NodeIn {
   const GraphDesc* desc;
   uint32_t G;
   const uint64_t* Q;
-  __device__ Triple load(uint64_t i) const {
-    const uint32_t g = find_graph(G, i, [&](uint32_t x) { return desc[x].r_off; });
+  struct Ctx {
+    const double* w;
+    const uint64_t* Qg;   // the graph's quantised prefix relative to Qbase
+    double S, qscale;
+    uint64_t n, u_begin, nr, r_off, Qbase, Qn;
+  };
+  __device__ uint32_t graph_of(uint64_t i) const {
+    return find_graph(G, i, [&](uint32_t x) { return desc[x].r_off; });
+  }
+  __device__ Ctx context(uint32_t g) const {
     const GraphDesc& d = desc[g];
-    const uint64_t r = i - d.r_off;
-    const uint64_t nr = d.u_end - d.u_begin;
-    if (r >= nr) return Triple{0, 0, 0};
-    const uint64_t u = d.u_begin + r;
+    return Ctx{d.w, Q + d.q_off, d.S, d.qscale, d.n, d.u_begin, d.u_end - d.u_begin, d.r_off, d.Qbase,
+               d.Qend - d.Qbase};
+  }
+  __device__ Triple load(uint64_t i, const Ctx& c) const {
+    const uint64_t r = i - c.r_off;
+    if (r >= c.nr) return Triple{0, 0, 0};
+    const uint64_t u = c.u_begin + r;
     uint32_t K = 1;
     double eh = 0.0;
-    if (d.qscale != 0.0 && u + 1 < d.n) {
-      const double a = d.w[u] / d.S;
-      const uint64_t Qn = d.Qend - d.Qbase;
-      const uint64_t D = Qn - (Q[d.q_off + u + 1] - d.Qbase);
-      eh = ehat_of(a, D, d.qscale);
-      K = nseg_of(eh, d.n, u);
+    if (c.qscale != 0.0 && u + 1 < c.n) {
+      const double a = c.w[u] / c.S;
+      const uint64_t D = c.Qn - (c.Qg[u + 1] - c.Qbase);
+      eh = ehat_of(a, D, c.qscale);
+      K = nseg_of(eh, c.n, u);
     }
     double ce = eh * static_cast<double>(kCostUnit);
     if (ce > 0x1.0p36) ce = 0x1.0p36;
-    const uint64_t c = static_cast<uint64_t>(ce) + static_cast<uint64_t>(kCostUnit) * K;
-    return Triple{c, K, (K > 1) ? 1ull : 0ull};
+    const uint64_t cost = static_cast<uint64_t>(ce) + static_cast<uint64_t>(kCostUnit) * K;
+    return Triple{cost, K, (K > 1) ? 1ull : 0ull};
   }
 };
 
@@ -279,21 +321,26 @@ struct NodeOut {
   uint32_t G;
   uint64_t* C;
   uint64_t* SB;
-  __device__ void store(uint64_t i, Triple, Triple ex) const {
+  struct Ctx {
+    GraphDesc* d;
+    uint64_t r_off, nr;
+  };
+  __device__ Ctx context(uint32_t g) const {
+    return Ctx{desc + g, desc[g].r_off, desc[g].u_end - desc[g].u_begin};
+  }
+  __device__ void store(uint64_t i, const Ctx& c, Triple, Triple ex) const {
     C[i] = ex.c;
     SB[i] = ex.k;
-    const uint32_t g = find_graph(G, i, [&](uint32_t x) { return desc[x].r_off; });
-    GraphDesc& d = desc[g];
-    const uint64_t r = i - d.r_off;
+    const uint64_t r = i - c.r_off;
     if (r == 0) {
-      d.C0 = ex.c;
-      d.SB0 = ex.k;
-      d.H0 = ex.h;
+      c.d->C0 = ex.c;
+      c.d->SB0 = ex.k;
+      c.d->H0 = ex.h;
     }
-    if (r == d.u_end - d.u_begin) {
-      d.C1 = ex.c;
-      d.SB1 = ex.k;
-      d.H1 = ex.h;
+    if (r == c.nr) {
+      c.d->C1 = ex.c;
+      c.d->SB1 = ex.k;
+      c.d->H1 = ex.h;
     }
   }
 };
@@ -374,16 +421,17 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
     const uint64_t K = hdr->SB[d.r_off + r + 1] - hdr->SB[d.r_off + r];
     const uint64_t k = hl - sb;
     const uint64_t u = d.u_begin + r;
-    uint64_t b;
-    if (k == 0) {
-      b = u + 1;
-    } else {
-      const uint64_t base = hdr->Q[d.q_off + u + 1] - d.Qbase;
-      const uint64_t Dm = (d.Qend - d.Qbase) - base;
-      const uint64_t target = k * (Dm / K) + (k * (Dm % K)) / K;
-      b = q_lower_bound(hdr->Q, d.q_off, d.Qbase, u + 1, d.n, base + target);
-    }
-    hdr->hseg[h] = static_cast<uint32_t>(b);
+    const uint64_t base = hdr->Q[d.q_off + u + 1] - d.Qbase;
+    const uint64_t Dm = (d.Qend - d.Qbase) - base;
+    // b_kk: first candidate of segment kk (b_0 = u + 1; the last segment ends at n)
+    auto bound = [&](uint64_t kk) -> uint64_t {
+      if (kk == 0) return u + 1;
+      if (kk >= K) return d.n;
+      const uint64_t target = kk * (Dm / K) + (kk * (Dm % K)) / K;
+      return q_lower_bound(hdr->Q, d.q_off, d.Qbase, u + 1, d.n, base + target);
+    };
+    hdr->hseg[h] = HSeg{static_cast<uint32_t>(u), static_cast<uint32_t>(k), static_cast<uint32_t>(bound(k)),
+                        static_cast<uint32_t>(bound(k + 1))};
   }
 }
 
@@ -424,8 +472,7 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
       double kk = ceil((Ti - static_cast<double>(cex)) * static_cast<double>(K) / cnode) - 1.0;
       if (!(kk > 0.0)) kk = 0.0;
       if (kk > static_cast<double>(K - 1)) kk = static_cast<double>(K - 1);
-      hdr->lane_start[d.lane_off + li] =
-          make_uint2(static_cast<uint32_t>(d.u_begin + r), static_cast<uint32_t>(kk));
+      hdr->lane_seg[d.lane_off + li] = static_cast<uint32_t>(hdr->SB[i] - d.SB0 + static_cast<uint64_t>(kk));
       if (hdr->lane_cum) {
         // plan cost before the lane's first segment (segments of a source share its cost equally)
         const double before = static_cast<double>(cex) + kk * cnode / static_cast<double>(K);
@@ -451,7 +498,7 @@ __global__ void __launch_bounds__(256) k_lane_groups(const WsHeader* hdr) {
     hdr->group_graph[q] = g;
     for (uint64_t li = (l0 - d.lane_off); li < (l0 - d.lane_off) + kLaneGroup; ++li) {
       if (li >= d.L) {
-        hdr->lane_start[d.lane_off + li] = make_uint2(static_cast<uint32_t>(d.u_end), 0u);
+        hdr->lane_seg[d.lane_off + li] = static_cast<uint32_t>(d.SB1 - d.SB0);
         if (hdr->lane_cum) hdr->lane_cum[d.lane_off + li] = d.C1 - d.C0;
       }
     }
@@ -471,6 +518,17 @@ __device__ __forceinline__ gptr<T> to_global(const T* p) {
   return (gptr<T>)(p);
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// writable global pointers (stores with immediate offsets, no LDS aperture check)
+template <class T>
+using gout = T __attribute__((address_space(1)))*;
+
+template <class T>
+__device__ __forceinline__ gout<T> to_global_mut(T* p) {
+  return (gout<T>)(p);
+}
+
 // wave-uniform copies of values that are equal on every lane (they then live
 // in scalar registers)
 __device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -484,99 +542,100 @@ template <class T>
 __device__ __forceinline__ const T* uniptr(const T* p) {
   return reinterpret_cast<const T*>(uni64(reinterpret_cast<uint64_t>(p)));
 }
+template <class T>
+__device__ __forceinline__ T* uniptr_mut(T* p) {
+  return reinterpret_cast<T*>(uni64(reinterpret_cast<uint64_t>(p)));
+}
 
 struct LaneCtx {
   gptr<double> w;
   gptr<double> A;                 // a_u = w_u / S of the range's sources (index u - u_begin)
   uint32_t n;
   uint32_t u_begin, u_heavy_end;  // sources [u_begin, u_heavy_end) are heavy
-  gptr<uint64_t> SB;              // source prefix of segment counts (graph's r_off applied)
-  uint64_t SB0;
-  gptr<uint32_t> hseg;            // graph's heavy table
+  uint32_t NH;                    // heavy segments; segment index NH + i is light source u_heavy_end + i
+  gptr<u32x4> hseg;               // graph's heavy segments (u, k, j, send)
 };
 
-// Runs the segments of one lane from (u, k) up to (ue, ke) (exclusive) and
-// reports each kept edge through emit(u, v); emit returns false to stop.
-// All lanes of the wavefront iterate together; a lane that has finished its
-// segment opens the next one at the top of the loop.
-template <class Emit>
-__device__ __forceinline__ void run_lane(const LaneCtx& cx, const RoundKeys& rk, const Series& sr, uint32_t u,
-                                         uint32_t k, uint32_t ue, uint32_t ke, Emit& emit, uint32_t& visits) {
-  bool more = (u < ue) || (u == ue && k < ke);
-  bool inseg = false;
-  uint32_t su = 0, sk = 0;   // source and segment of the open segment
-  uint32_t j = 0, send = 0, t = 0;
-  double a = 0.0, p = 0.0;
-  while (true) {
-    if (!inseg && more) {
-      su = u;
-      sk = k;
-      const uint32_t r = u - cx.u_begin;
-      a = cx.A[r];
-      uint32_t K = 1;
-      if (u < cx.u_heavy_end) {
-        const uint64_t sb = cx.SB[r] - cx.SB0;
-        K = static_cast<uint32_t>(cx.SB[r + 1] - cx.SB[r]);
-        j = cx.hseg[sb + k];
-        send = (k + 1 < K) ? cx.hseg[sb + k + 1] : cx.n;
-      } else {
-        j = u + 1;
-        send = cx.n;
-      }
-      t = 0;
-      p = (j < send) ? cap1(a * cx.w[j]) : 0.0;
-      inseg = (p > 0.0);
-      ++k;
-      if (k >= K) {
-        k = 0;
-        ++u;
-      }
-      more = (u < ue) || (u == ue && k < ke);
-    }
-    if (!__any(inseg || more)) break;
-    if (inseg) {
-      // candidate step of Alg. 1: skip, then accept with probability q/p
-      const bool capped = (p == 1.0);
-      double wv_c = 0.0;
-      if (capped) wv_c = cx.w[j];
-      const bool need_rng = !capped || !(a * wv_c >= 1.0);
-      Block4 x{0u, 0u, 0u, 0u};
-      if (need_rng) x = philox10(t, sk, su, 0u, rk);
-      ++t;
-      bool stop = false;
-      uint32_t v = j;
-      double q;
-      if (capped) {
-        q = cap1(a * wv_c);
-      } else {
-        const double r_skip = unit53(x.x1, x.x0);
-        const double ratio = ln_unit(r_skip, sr) / ln_one_minus(p, sr);
-        if (!(ratio < static_cast<double>(send - j))) {
-          stop = true;
-          q = 0.0;
-        } else {
-          v = j + static_cast<uint32_t>(ratio);
-          q = cap1(a * cx.w[v]);
-        }
-      }
-      if (!stop) {
-        ++visits;
-        const double r_acc = unit53(x.x3, x.x2);
-        const bool keep = capped ? (q == 1.0 || r_acc * p < q) : (r_acc * p < q);
-        if (keep) {
-          if (!emit(su, v)) {
-            inseg = false;
-            more = false;
-            continue;
-          }
-        }
-        p = q;
-        j = v + 1;
-        if (j >= send || !(p > 0.0)) stop = true;
-      }
-      if (stop) inseg = false;
-    }
+// State of one lane inside its current work unit: the unit is the run of
+// segments [sg, sg_end) of the lane plan (graph-relative segment indices);
+// (u, k) is the open segment, j its next candidate, send its end, t the index
+// of its next draw.
+struct LaneRun {
+  uint32_t sg, sg_end;
+  uint32_t u, k, j, send, t;
+  double a, p;
+  bool inseg;
+  __device__ bool more() const { return sg < sg_end; }
+};
+
+// Opens segment sg (Alg. 1 set-up of source u, segment k).
+__device__ __forceinline__ void open_segment(LaneRun& s, const LaneCtx& cx) {
+  const uint32_t sg = s.sg;
+  if (sg < cx.NH) {
+    const u32x4 d = cx.hseg[sg];
+    s.u = d.x;
+    s.k = d.y;
+    s.j = d.z;
+    s.send = d.w;
+  } else {
+    s.u = cx.u_heavy_end + (sg - cx.NH);
+    s.k = 0;
+    s.j = s.u + 1;
+    s.send = cx.n;
   }
+  s.a = cx.A[s.u - cx.u_begin];
+  const bool any = s.j < s.send;
+  const double wj = cx.w[any ? s.j : 0u];
+  s.p = any ? cap1(s.a * wj) : 0.0;
+  s.inseg = (s.p > 0.0);
+  s.t = 0;
+  ++s.sg;
+}
+
+// ln(1 - p) of ln_one_minus without the branch: both forms share one division
+// and one series evaluation, the operands are selected.  Bit-identical to
+// ln_one_minus for p in (0, 1); for p = 1 it returns a finite value.
+__device__ __forceinline__ double ln_one_minus_sel(double p, const Series& sr) {
+  const bool small = p < 0.25;
+  double m;
+  int e;
+  log_reduce(1.0 - p, m, e);
+  const double f = m - 1.0;
+  const double num = small ? -p : f;
+  const double den = small ? 2.0 - p : 2.0 + f;
+  const double l = two_s_series(num / den, sr);
+  return small ? l : (static_cast<double>(e) * 0x1.62e42fefa39efp-1) + l;
+}
+
+// One candidate step of Alg. 1 on the open segment: geometric skip with
+// r_skip, then accept with probability q/p using r_acc (draw t of segment
+// (u, k)); a capped segment (p = 1) takes the next candidate without a skip.
+// Straight-line apart from the emission.  Kept edges go to emit(u, v); emit
+// returns false to end the unit.
+template <class Emit>
+__device__ __forceinline__ void candidate_step(LaneRun& s, const LaneCtx& cx, const RoundKeys& rk,
+                                               const Series& sr, Emit& emit, uint32_t& visits) {
+  const bool capped = (s.p == 1.0);
+  const Block4 x = philox10(s.t, s.k, s.u, 0u, rk);
+  ++s.t;
+  const double lr = ln_unit(unit53(x.x1, x.x0), sr);
+  const double ratio = lr / ln_one_minus_sel(s.p, sr);
+  const bool leaves = !capped && !(ratio < static_cast<double>(s.send - s.j));   // the skip leaves the segment
+  const uint32_t v = s.j + ((capped || leaves) ? 0u : static_cast<uint32_t>(ratio));
+  const double q = cap1(s.a * cx.w[v]);    // v < send <= n, or v = j < send
+  const double r_acc = unit53(x.x3, x.x2);
+  const bool keep = !leaves && ((capped && q == 1.0) || (r_acc * s.p < q));
+  if (keep && !emit(s.u, v)) {
+    s.inseg = false;
+    s.sg = s.sg_end;
+    return;
+  }
+  if (!leaves) {
+    ++visits;
+    s.p = q;
+    s.j = v + 1;
+  }
+  s.inseg = !(leaves || s.j >= s.send || !(s.p > 0.0));
 }
 
 struct CountEmit {
@@ -588,35 +647,40 @@ struct CountEmit {
 };
 
 // Write-pass output through LDS: every lane stages its edges in 64-byte
-// chunks of the output (8 pairs, aligned to the window start) and stores a
-// chunk once it is complete, as four 16-byte stores, so that HBM receives
+// chunks of the output (8 pairs, aligned to the window start lo) and stores
+// a chunk once it is complete, as four 16-byte stores, so that HBM receives
 // whole 64-byte sectors instead of the 8-byte pieces of 64 interleaved lane
-// streams.  Chunks a lane shares with its neighbours (its first and last) are
-// stored pair by pair.  LDS layout [slot][thread] keeps the per-emission
-// stores of a wavefront free of bank conflicts.
+// streams.  Chunks a lane shares with its neighbours (the first and last of
+// a unit) are stored pair by pair.  LDS layout [slot][thread] keeps the
+// per-emission stores of a wavefront free of bank conflicts.
 constexpr int kStageSlots = 8;
+constexpr int kLaneThreads = 256;   // block size of the lane kernels
 
 struct WriteEmit {
-  uint2* stage;      // LDS, kStageSlots x blockDim entries
-  uint32_t tid;      // thread in block
-  uint32_t nthr;     // blockDim.x
-  uint2* out;        // output window: out[i] is position lo + i
-  uint64_t pos, lo, hi, first;
-  __device__ uint2& slot(uint64_t q) { return stage[(q & (kStageSlots - 1)) * nthr + tid]; }
-  __device__ void flush(uint64_t q0, uint64_t qend) {
-    // chunk [q0, q0 + 8) of the window; the lane owns entries [max(q0, first), qend)
-    const uint64_t f = (first > lo) ? first - lo : 0;
-    const uint64_t s0 = (q0 > f) ? q0 : f;
-    if (s0 == q0 && qend == q0 + kStageSlots) {
-      uint4* dst = reinterpret_cast<uint4*>(out + q0);
+  uint2* stage;      // LDS, kStageSlots x kLaneThreads entries
+  gout<uint2> out;   // output window: out[i] is position lo + i (uniform)
+  uint64_t lo;       // window start (uniform)
+  uint64_t pos, hi;  // next position, end of the unit's range
+  uint32_t run;      // entries staged by this unit (saturates at kStageSlots)
+  __device__ uint2& slot(uint64_t q) { return stage[(q & (kStageSlots - 1)) * kLaneThreads + threadIdx.x]; }
+  // stores the lane's entries of the chunk that ends at qend (exclusive):
+  // the whole chunk if the lane staged all of it, else its last `own` entries
+  __device__ void flush(uint64_t qend, uint32_t own) {
+    const uint64_t q0 = (qend - 1) & ~static_cast<uint64_t>(kStageSlots - 1);
+    if (own == kStageSlots) {
+      gout<u32x4> dst = reinterpret_cast<gout<u32x4>>(out + q0);
 #pragma unroll
       for (int i = 0; i < kStageSlots / 2; ++i) {
-        const uint2 x0 = stage[(2 * i) * nthr + tid];
-        const uint2 x1 = stage[(2 * i + 1) * nthr + tid];
-        dst[i] = make_uint4(x0.x, x0.y, x1.x, x1.y);
+        const uint2 x0 = stage[(2 * i) * kLaneThreads + threadIdx.x];
+        const uint2 x1 = stage[(2 * i + 1) * kLaneThreads + threadIdx.x];
+        dst[i] = u32x4{x0.x, x0.y, x1.x, x1.y};
       }
     } else {
-      for (uint64_t q = s0; q < qend; ++q) out[q] = slot(q);
+      gout<uint64_t> o = reinterpret_cast<gout<uint64_t>>(out);
+      for (uint64_t q = qend - own; q < qend; ++q) {
+        const uint2 x = slot(q);
+        o[q] = (static_cast<uint64_t>(x.y) << 32) | x.x;
+      }
     }
   }
   __device__ bool operator()(uint32_t u, uint32_t v) {
@@ -624,121 +688,199 @@ struct WriteEmit {
     if (pos >= lo) {
       const uint64_t q = pos - lo;
       slot(q) = make_uint2(u, v);
-      if ((q & (kStageSlots - 1)) == kStageSlots - 1) flush(q - (kStageSlots - 1), q + 1);
+      if (run < kStageSlots) ++run;
+      if ((q & (kStageSlots - 1)) == kStageSlots - 1) {
+        // a chunk the lane started mid-way holds only its last `run` entries
+        flush(q + 1, run);
+        run = kStageSlots;
+      }
     }
     ++pos;
     return true;
   }
-  // the lane's last, incomplete chunk
+  // the unit's last, incomplete chunk
   __device__ void finish() {
     const uint64_t end = (pos < hi) ? pos : hi;
     if (end > lo) {
       const uint64_t q = end - lo;
-      if (q & (kStageSlots - 1)) flush(q & ~static_cast<uint64_t>(kStageSlots - 1), q);
+      const uint32_t part = static_cast<uint32_t>(q & (kStageSlots - 1));
+      if (part) flush(q, (run < part) ? run : part);
     }
   }
 };
 
 // One-pass output: the lane counts every kept edge and writes the first
-// `cap` of them into its slot (64-byte aligned), staged like WriteEmit.
+// `cap` of them into the unit's slot (64-byte aligned), staged like WriteEmit.
 struct SlotEmit {
-  WriteEmit wr;      // window = the slot
+  WriteEmit wr;      // window = all slots (lo = 0); the unit writes [pos, hi)
   uint32_t c;
+  bool over;         // an edge did not fit
   __device__ bool operator()(uint32_t u, uint32_t v) {
     ++c;
-    if (wr.pos < wr.hi) wr(u, v);
+    if (wr.pos < wr.hi)
+      wr(u, v);
+    else
+      over = true;
     return true;
   }
 };
 
-// kMode 0: count pass.  kMode 1: write pass (replay into the output window;
-// in one-pass plans only the lanes that overflowed their slot).  kMode 2:
-// one pass, count and write into slots.
 template <int kMode>
-__global__ void __launch_bounds__(256) k_lanes(WsHeader* hdr, uint2* out, uint64_t e_lo, uint64_t e_hi) {
+struct EmitOf {
+  using type = SlotEmit;
+};
+template <>
+struct EmitOf<0> {
+  using type = CountEmit;
+};
+template <>
+struct EmitOf<1> {
+  using type = WriteEmit;
+};
+
+// The lane kernel.  kMode 0: count pass.  kMode 1: write pass (replay into
+// the output window; in one-pass plans only the units that overflowed their
+// slot).  kMode 2: one pass, count and write into slots.
+//
+// Scheduling: the work units of the lane plan (Eq. 5 applied to lanes) are
+// handed out dynamically.  A wavefront takes chunks of 64 consecutive units
+// (all of one graph) from a global ticket counter, and each of its lanes takes
+// the next unit of the chunk as soon as it has finished its previous one, so a
+// lane never waits for the slowest lane of a fixed group.  The lanes of a
+// wavefront work on one graph at a time (its parameters live in scalar
+// registers); a chunk of another graph is handed out once every lane is idle.
+template <int kMode>
+__global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* out, uint64_t e_lo, uint64_t e_hi) {
+  using Emit = typename EmitOf<kMode>::type;
   constexpr bool kWrite = (kMode != 0);
-  __shared__ uint2 stage[kWrite ? kStageSlots * 256 : 1];
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  __shared__ uint2 stage[kWrite ? kStageSlots * kLaneThreads : 1];
   if (hdr->status || hdr->magic != kWsMagic) return;
   if (kMode == 1 && !hdr->planned) return;
   const bool only_overflow = (kMode == 1) && (uni32(hdr->mode) == 1);
   if (only_overflow && uni32(hdr->overflow) == 0) return;
   const GraphDesc* desc = hdr->desc;
-  const uint64_t ngroups = uni64(hdr->total_nl) / kLaneGroup;
+  const uint32_t ngroups = uni32(static_cast<uint32_t>(uni64(hdr->total_nl) / kLaneGroup));
   const Series sr = load_series();
   const int lane = threadIdx.x & 63;
-  uint64_t visited = 0;   // candidates visited by this lane over all its work items (count pass)
-  // The loop body has no lane-divergent region that is not closed inside it:
-  // the ticket is fetched by lane 0, broadcast to every lane (so the value is
-  // uniform before readfirstlane marks it so for the compiler), and the only
-  // other single-lane action (the candidate total) is done after the loop.
+  // workspace arrays, read once into scalar registers
+  const gptr<uint32_t> lane_seg = to_global(uniptr(hdr->lane_seg));
+  const gout<uint32_t> lane_cnt = to_global_mut(uniptr_mut(hdr->lane_cnt));
+  const gptr<uint64_t> slot_off = to_global(uniptr(hdr->slot_off));
+  const gptr<uint64_t> lane_pos = to_global(uniptr(hdr->lane_pos));
+  const gptr<uint32_t> group_graph = to_global(uniptr(hdr->group_graph));
+  const gout<uint2> slots = to_global_mut(uniptr_mut(hdr->slots));
+  const gout<uint2> outw = to_global_mut(uniptr_mut(out));
+  unsigned int* overflow = &hdr->overflow;
+
+  // wave-uniform: the graph bound to the wavefront, its parameters, the chunk
+  uint32_t g_cur = kNone;
+  LaneCtx cx{};
+  RoundKeys rk{};
+  uint64_t unit_end = 0;     // one past the graph's last (padded) unit
+  uint32_t nseg = 0;         // segments of the graph
+  uint32_t cnext = 0, cend = 0, cgraph = kNone;
+  bool queue_done = false;
+
+  // per lane
+  uint32_t unit = kNone;
+  bool touched = false;      // write pass: the unit writes into the window
+  uint32_t visits = 0;
+  LaneRun s{};
+  s.sg = 0;
+  s.sg_end = 0;
+  s.inseg = false;
+  Emit em{};
+
   while (true) {
-    uint32_t grp = 0;
-    if (lane == 0) grp = atomicAdd(&hdr->queue, 1u);
-    grp = static_cast<uint32_t>(__shfl(static_cast<int>(grp), 0, 64));
-    grp = uni32(grp);
-    if (grp >= ngroups) break;
-    const uint32_t g = uni32(hdr->group_graph[grp]);
-    const GraphDesc& d = desc[g];
-    const uint64_t lane_off = uni64(d.lane_off), NL = uni64(d.NL);
-    const uint32_t u_end = uni32(static_cast<uint32_t>(d.u_end));
-    const uint64_t l = static_cast<uint64_t>(grp) * kLaneGroup + lane;
-    const uint2 st = hdr->lane_start[l];
-    uint2 en = make_uint2(u_end, 0u);
-    if (l + 1 < lane_off + NL) en = hdr->lane_start[l + 1];
-    LaneCtx cx;
-    cx.w = to_global(uniptr(d.w));
-    cx.n = uni32(static_cast<uint32_t>(d.n));
-    cx.u_begin = uni32(static_cast<uint32_t>(d.u_begin));
-    cx.u_heavy_end = cx.u_begin + uni32(static_cast<uint32_t>(d.H));
-    const uint64_t r_off = uni64(d.r_off);
-    cx.A = to_global(uniptr(hdr->A) + r_off);
-    cx.SB = to_global(uniptr(hdr->SB) + r_off);
-    cx.SB0 = uni64(d.SB0);
-    cx.hseg = to_global(uniptr(hdr->hseg) + uni64(d.hs_off));
-    const RoundKeys rk = philox_round_keys(uni64(d.seed));
-    if (kMode == 2) {
-      const uint64_t s0 = hdr->slot_off[l];
-      const uint64_t s1 = hdr->slot_off[l + 1];
-      // the writer indexes its window from the window start: out[i] is slot position s0 + i
-      SlotEmit em{WriteEmit{stage, threadIdx.x, blockDim.x, hdr->slots + s0, s0, s0, s1, s0}, 0u};
-      uint32_t visits = 0;
-      run_lane(cx, rk, sr, st.x, st.y, en.x, en.y, em, visits);
-      em.wr.finish();
-      hdr->lane_cnt[l] = em.c;
-      if (em.c > s1 - s0) atomicAdd(&hdr->overflow, 1u);
-      visited += visits;
-    } else if (kMode == 1) {
-      const uint64_t pos0 = hdr->lane_pos[l];
-      const uint64_t cnt = hdr->lane_cnt[l];
-      bool touches = (pos0 < e_hi) && (pos0 + cnt > e_lo);
-      if (only_overflow) touches = touches && (cnt > hdr->slot_off[l + 1] - hdr->slot_off[l]);
-      if (__any(touches)) {
-        WriteEmit em{stage, threadIdx.x, blockDim.x, out, pos0, e_lo, e_hi, pos0};
-        uint32_t su = st.x, sk = st.y, eu = en.x, ek = en.y;
-        if (!touches) {
-          eu = su;
-          ek = sk;
-        }
-        uint32_t visits = 0;
-        run_lane(cx, rk, sr, su, sk, eu, ek, em, visits);
-        if (touches) em.finish();
+    // (1) a lane that has finished its unit closes it
+    const bool idle = !(s.inseg || s.more());
+    if (idle && unit != kNone) {
+      if constexpr (kMode == 0) {
+        lane_cnt[unit] = em.c;
+      } else if constexpr (kMode == 2) {
+        em.wr.finish();
+        lane_cnt[unit] = em.c;
+        if (em.over) atomicAdd(overflow, 1u);
+      } else {
+        if (touched) em.finish();
       }
-    } else {
-      CountEmit em{0u};
-      uint32_t visits = 0;
-      run_lane(cx, rk, sr, st.x, st.y, en.x, en.y, em, visits);
-      hdr->lane_cnt[l] = em.c;
-      visited += visits;
+      unit = kNone;
     }
+    // (2) idle lanes take the next units of the wavefront's chunk
+    const uint64_t idle_mask = __ballot(idle);
+    if (idle_mask != 0 && !(queue_done && cnext >= cend)) {
+      if (cnext >= cend) {
+        uint32_t grp = 0;
+        if (lane == 0) grp = atomicAdd(&hdr->queue, 1u);
+        grp = uni32(static_cast<uint32_t>(__shfl(static_cast<int>(grp), 0, 64)));
+        if (grp >= ngroups) {
+          queue_done = true;
+        } else {
+          cnext = grp * kLaneGroup;
+          cend = cnext + kLaneGroup;
+          cgraph = uni32(group_graph[grp]);
+        }
+      }
+      if (cnext < cend && (cgraph == g_cur || idle_mask == ~0ull)) {
+        if (cgraph != g_cur) {
+          g_cur = cgraph;
+          const GraphDesc& d = desc[g_cur];
+          cx.w = to_global(uniptr(d.w));
+          cx.n = uni32(static_cast<uint32_t>(d.n));
+          cx.u_begin = uni32(static_cast<uint32_t>(d.u_begin));
+          cx.u_heavy_end = cx.u_begin + uni32(static_cast<uint32_t>(d.H));
+          cx.NH = uni32(static_cast<uint32_t>(d.NH));
+          cx.A = to_global(uniptr(hdr->A) + uni64(d.r_off));
+          cx.hseg = to_global(reinterpret_cast<const u32x4*>(uniptr(hdr->hseg) + uni64(d.hs_off)));
+          rk = philox_round_keys(uni64(d.seed));
+          unit_end = uni64(d.lane_off) + uni64(d.NL);
+          nseg = uni32(static_cast<uint32_t>(d.SB1 - d.SB0));
+        }
+        // rank of this lane among the idle lanes
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(idle_mask >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(idle_mask), 0u));
+        const uint32_t mine = cnext + rank;
+        if (idle && mine < cend) {
+          unit = mine;
+          s.sg = lane_seg[unit];
+          s.sg_end = (unit + 1 < unit_end) ? lane_seg[unit + 1] : nseg;
+          s.inseg = false;
+          if constexpr (kMode == 0) {
+            em = Emit{0u};
+          } else if constexpr (kMode == 2) {
+            const uint64_t s0 = slot_off[unit];
+            const uint64_t s1 = slot_off[unit + 1];
+            em.wr = WriteEmit{stage, slots, 0ull, s0, s1, 0u};
+            em.c = 0u;
+            em.over = false;
+          } else {
+            const uint64_t pos0 = lane_pos[unit];
+            const uint64_t cnt = lane_cnt[unit];
+            touched = (pos0 < e_hi) && (pos0 + cnt > e_lo);
+            if (only_overflow) touched = touched && (cnt > slot_off[unit + 1] - slot_off[unit]);
+            em = WriteEmit{stage, outw, e_lo, pos0, e_hi, 0u};
+            if (!touched) s.sg_end = s.sg;
+          }
+        }
+        const uint32_t handed = static_cast<uint32_t>(__popcll(idle_mask));
+        cnext = (cend - cnext > handed) ? cnext + handed : cend;
+      }
+    }
+    // (3) open the next segment of the unit
+    if (!s.inseg && s.more()) open_segment(s, cx);
+    if (!__any(s.inseg || s.more() || unit != kNone) && queue_done && cnext >= cend) break;
+    // (4) one candidate step
+    if (s.inseg) candidate_step(s, cx, rk, sr, em, visits);
   }
   if (kMode != 1) {
     // candidates visited by the wavefront (statistics of the cost model)
+    uint64_t visited = visits;
     for (int dd = 32; dd >= 1; dd >>= 1) visited += shfl_idx64(visited, lane ^ dd);
     if (lane == 0)
       atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->total_cand), static_cast<unsigned long long>(visited));
   }
 }
-
 // --------------------------------------------------------------------------
 // one-pass slots: capacity of a lane = its plan cost mu (in expected
 // candidates, which bounds its expected edges) + 8 sqrt(mu) + 24, rounded up
@@ -747,24 +889,33 @@ __global__ void __launch_bounds__(256) k_lanes(WsHeader* hdr, uint2* out, uint64
 // --------------------------------------------------------------------------
 struct SlotIn {
   const WsHeader* hdr;
-  uint64_t nl;
-  __device__ uint64_t load(uint64_t l) const {
-    if (l >= nl) return 0;
-    const GraphDesc& d = hdr->desc[hdr->group_graph[l / kLaneGroup]];
-    const uint64_t i = l - d.lane_off;
-    if (i >= d.L) return 0;
-    const uint64_t c1 = (i + 1 < d.L) ? hdr->lane_cum[l + 1] : (d.C1 - d.C0);
+  struct Ctx {
+    uint64_t nl;        // lanes of all graphs (padded)
+    uint64_t lane_off, L, Z;
+  };
+  __device__ uint32_t graph_of(uint64_t l) const {
+    return (l < hdr->total_nl) ? hdr->group_graph[l / kLaneGroup] : 0u;
+  }
+  __device__ Ctx context(uint32_t g) const {
+    const GraphDesc& d = hdr->desc[g];
+    return Ctx{hdr->total_nl, d.lane_off, d.L, d.C1 - d.C0};
+  }
+  __device__ uint64_t load(uint64_t l, const Ctx& c) const {
+    if (l >= c.nl) return 0;
+    const uint64_t i = l - c.lane_off;
+    if (i >= c.L) return 0;
+    const uint64_t c1 = (i + 1 < c.L) ? hdr->lane_cum[l + 1] : c.Z;
     const uint64_t c0 = hdr->lane_cum[l];
     const double mu = static_cast<double>(c1 > c0 ? c1 - c0 : 0) / static_cast<double>(kCostUnit);
     const double cap = (hdr->slot_margin == 1) ? mu : (mu + 8.0 * sqrt(mu) + 24.0);
-    const uint64_t c = static_cast<uint64_t>(ceil(cap));
-    return (c + kStageSlots - 1) / kStageSlots * kStageSlots;
+    const uint64_t cc = static_cast<uint64_t>(ceil(cap));
+    return (cc + kStageSlots - 1) / kStageSlots * kStageSlots;
   }
 };
 
-struct SlotOut {
+struct SlotOut : OneGraph {
   uint64_t* off;
-  __device__ void store(uint64_t i, uint64_t, uint64_t ex) const { off[i] = ex; }
+  __device__ void store(uint64_t i, Ctx, uint64_t, uint64_t ex) const { off[i] = ex; }
 };
 
 __global__ void k_slot_check(WsHeader* hdr) {
@@ -803,15 +954,15 @@ __global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out
 // --------------------------------------------------------------------------
 // offsets of the lanes' output
 // --------------------------------------------------------------------------
-struct CntIn {
+struct CntIn : OneGraph {
   const uint32_t* cnt;
   uint64_t n;
-  __device__ uint64_t load(uint64_t i) const { return (i < n) ? cnt[i] : 0; }
+  __device__ uint64_t load(uint64_t i, Ctx) const { return (i < n) ? cnt[i] : 0; }
 };
 
-struct OffOut {
+struct OffOut : OneGraph {
   uint64_t* off;
-  __device__ void store(uint64_t i, uint64_t, uint64_t ex) const { off[i] = ex; }
+  __device__ void store(uint64_t i, Ctx, uint64_t, uint64_t ex) const { off[i] = ex; }
 };
 
 __global__ void __launch_bounds__(256) k_graph_edges(WsHeader* hdr, uint64_t* m_dev) {

@@ -50,6 +50,11 @@ struct Triple {
   uint64_t c, k, h;  // cost units, segments, heavy sources
 };
 
+// one segment of a heavy source: candidates [j, send) of source u, segment k
+struct HSeg {
+  uint32_t u, k, j, send;
+};
+
 // Pointers into the workspace; copied into the workspace header so that
 // later calls need only the workspace base.
 struct WsHeader {
@@ -65,8 +70,8 @@ struct WsHeader {
   double* A;          // [total_r] a_u = w_u / S per source of the range
   uint64_t* scan_tmp; // scan partials
   uint64_t scan_tmp_elems;
-  uint32_t* hseg;     // [cap_nh] heavy segment starts
-  uint2* lane_start;  // [cap_nl] (u, k) of each lane's first segment
+  HSeg* hseg;         // [cap_nh] heavy segments (segment index order)
+  uint32_t* lane_seg; // [cap_nl] first segment (graph-relative index) of each lane
   uint32_t* lane_cnt; // [cap_nl]
   uint64_t* lane_pos; // [cap_nl + 1] exclusive prefix of lane_cnt (edge offsets)
   uint64_t* lane_scan_tmp;

@@ -30,24 +30,28 @@ struct ScanTraits<Dbl2> {
     return Dbl2{__longlong_as_double(static_cast<long long>(shfl_up64(static_cast<uint64_t>(__double_as_longlong(x.a)), d))),
                 __longlong_as_double(static_cast<long long>(shfl_up64(static_cast<uint64_t>(__double_as_longlong(x.b)), d)))};
   }
+  __device__ static Dbl2 shfl_idx(Dbl2 x, int src) {
+    return Dbl2{__longlong_as_double(static_cast<long long>(shfl_idx64(static_cast<uint64_t>(__double_as_longlong(x.a)), src))),
+                __longlong_as_double(static_cast<long long>(shfl_idx64(static_cast<uint64_t>(__double_as_longlong(x.b)), src)))};
+  }
 };
 
 // suffix sums of w and w^2: element i is w[n-1-i]; exclusive prefix at i is
 // sum_{y > n-1-i} w_y, i.e. the suffix from v = n - i.
-struct SufIn {
+struct SufIn : OneGraph {
   const double* w;
   uint64_t n;
-  __device__ Dbl2 load(uint64_t i) const {
+  __device__ Dbl2 load(uint64_t i, Ctx) const {
     if (i >= n) return Dbl2{0.0, 0.0};
     const double x = w[n - 1 - i];
     return Dbl2{x, x * x};
   }
 };
 
-struct SufOut {
+struct SufOut : OneGraph {
   Dbl2* suf;  // suf[v] = (sum_{y >= v} w_y, sum_{y >= v} w_y^2), v in [0, n]
   uint64_t n;
-  __device__ void store(uint64_t i, Dbl2, Dbl2 ex) const { suf[n - i] = ex; }
+  __device__ void store(uint64_t i, Ctx, Dbl2, Dbl2 ex) const { suf[n - i] = ex; }
 };
 
 // per-source terms, reduced per block into partials
@@ -81,10 +85,10 @@ __global__ void __launch_bounds__(256) k_reduce_dbl2(const Dbl2* partials, uint3
 }
 
 // ------------------------------------------------------------- partition
-struct PartIn {
+struct PartIn : OneGraph {
   const GraphDesc* desc;
   const uint64_t* Q;
-  __device__ uint64_t load(uint64_t u) const {
+  __device__ uint64_t load(uint64_t u, Ctx) const {
     const GraphDesc& d = desc[0];
     if (u >= d.n) return 0;
     double e = 0.0;
@@ -99,9 +103,9 @@ struct PartIn {
   }
 };
 
-struct PartOut {
+struct PartOut : OneGraph {
   uint64_t* C;
-  __device__ void store(uint64_t i, uint64_t, uint64_t ex) const { C[i] = ex; }
+  __device__ void store(uint64_t i, Ctx, uint64_t, uint64_t ex) const { C[i] = ex; }
 };
 
 // n_k = first u with C_incl(u) = C[u+1] >= ceil(k Z / P), for k in [1, P-1]

@@ -43,7 +43,10 @@ def _gpu_edges(cg, w, S, seed, u0=0, u1=None, tuning=None, planner="cl_count"):
 def test_weight_sum_is_exact(cg):
     rng = np.random.default_rng(30)
     cases = [W.config_small(), np.array([1.0]), np.array([1e16, 1.0, 1.0]), np.array([3e-310, 2e-310, 1e-320]),
-             np.sort(rng.pareto(0.7, 100000) * 1e3)[::-1], np.zeros(5), np.array([1e308, 1e308])]
+             np.sort(rng.pareto(0.7, 100000) * 1e3)[::-1], np.zeros(5), np.array([1e308, 1e308]),
+             # round half to even, with and without a sticky bit far below
+             np.array([2.0 ** 53, 1.0]), np.array([2.0 ** 53 + 2, 1.0]), np.array([2.0 ** 53, 1.0, 2.0 ** -1000]),
+             np.array([2.0 ** 1000, 2.0 ** 947, 5e-324]), np.array([2.0 ** 1000, 2.0 ** 947])]
     for w in cases:
         wd = _to_dev(w)
         if not np.all(np.isfinite(np.sum(w))):
