@@ -9,9 +9,15 @@ writing), offsets, compaction of the slots into the contiguous edge list.
 `value` is edges generated per second.  Printed as one JSON line, with:
 
 * roofline: the one-pass generation kernel (Alg. 1 per lane, edges staged
-  into 64-byte chunks of per-lane slots), timed with HIP events on its stream;
-  algorithmic work = visited candidates x the sampling rule's operation count;
-  bound "alu" against 256 CU x 64 lanes x 2.4 GHz lane-operations per second;
+  into 64-byte chunks of per-lane slots), timed with HIP events on its stream.
+  Its bound is the memory system: every visited candidate reads one weight
+  w_v at an essentially random position (8 algorithmic bytes, one 64-byte
+  line from HBM or the Infinity Cache on an L2 miss) and every kept edge
+  writes 8 bytes.  achieved = (8 B x candidates + 8 B x edges) / launch time
+  against 8 TB/s; traffic = the kernel's measured HBM bytes (FETCH_SIZE +
+  WRITE_SIZE, scaled by a copy kernel of known size) from the committed
+  counter summary when it was taken on the current kernel source;
+  alu_view gives the same launch against the VALU peak;
 * hbm_write: bytes of edges written per second by that kernel and by the
   compaction copy, against 8 TB/s;
 * two_pass: the count-then-replay path (count pass, offsets, write pass);
@@ -30,11 +36,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-OPS_PER_CANDIDATE = 145          # operation count of one candidate step
+OPS_PER_CANDIDATE = 145          # operation count of one candidate step of the sampling rule
 PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 3.93e13 lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+BYTES_PER_CANDIDATE = 8           # w_v gathered
+BYTES_PER_EDGE = 8                # (u, v) uint32 pair written
 HBM_PEAK = 8.0e12                 # bytes/s
 METRIC = "edges/sec generated on 1 MI355X + % HBM write roofline; batched vs plain"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_write_pass_plain_1e7.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_generation_plain_1e7.json")
 KERNEL_SOURCES = ["cl_device.hpp", "cl_kernels.hpp", "cl_plan.hpp"]
 
 
@@ -71,7 +79,7 @@ def parse():
     ap.add_argument("--n", type=int, default=10_000_000, help="sources of the plain workload")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one plain device copy of 1 GiB (for counter scaling)")
+                    help="also run one plain device copy of 2 GiB (for counter scaling)")
     return ap.parse_args()
 
 
@@ -147,6 +155,8 @@ def main():
     ms_step = elapsed / args.steps * 1e3
     value = total_edges / elapsed
     achieved_ops = cand * OPS_PER_CANDIDATE / t_gen
+    alg_bytes = BYTES_PER_CANDIDATE * cand + BYTES_PER_EDGE * m
+    achieved_bw = alg_bytes / t_gen
     traffic = traffic_per_launch()
     result = {
         "metric": METRIC,
@@ -167,15 +177,23 @@ def main():
                    "heavy_segments": info["heavy_segments"], "path": "one pass into slots + compaction"},
         "roofline": {
             "kernel": "one-pass generation (k_lanes<2>)",
-            "bound": "alu",
+            "bound": "hbm",
+            "achieved": achieved_bw / 1e9,
+            "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s",
+            "frac": achieved_bw / HBM_PEAK,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": int(alg_bytes),
+            "per_unit": "8 B per visited candidate (w_v gather) + 8 B per edge written",
+            "candidates_per_launch": int(cand),
+            "launch_ms": t_gen * 1e3,
+        },
+        "alu_view": {
             "achieved": achieved_ops / 1e12,
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "Top/s",
             "frac": achieved_ops / PEAK_LANE_OPS,
-            "traffic": traffic,
             "ops_per_candidate": OPS_PER_CANDIDATE,
-            "candidates_per_launch": int(cand),
-            "launch_ms": t_gen * 1e3,
         },
         "hbm_write": {
             "generation_GBps": 8.0 * m / t_gen / 1e9,
@@ -193,13 +211,20 @@ def main():
         result["batched"] = bench_batched(args, cg, W, torch, np, dev)
 
     if args.copy_calibration:
-        x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        # a plain device copy of 2 GiB whose source is not in any cache (a
+        # 2 GiB fill of another buffer runs in between): its FETCH_SIZE and
+        # WRITE_SIZE read 2 GiB each when the counters are exact
+        n8 = 1 << 28
+        x = torch.empty(n8, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
+        z = torch.empty_like(x)
         x.fill_(1.0)
+        z.fill_(2.0)
         torch.cuda.synchronize()
         y.copy_(x)
         torch.cuda.synchronize()
-        result["copy_calibration_bytes"] = 2 * x.numel() * 8
+        result["copy_calibration_bytes"] = n8 * 8
+        del x, y, z
 
     if not args.no_cpu:
         result["cpu_baseline"] = bench_cpu(w_np, seed)

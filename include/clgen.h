@@ -69,7 +69,7 @@ typedef struct cl_graph {
  * Zero fields take the defaults. */
 typedef struct cl_tuning {
   uint32_t lane_budget;    /* expected candidates per lane (Eq. 5 chunk size), default 192 */
-  uint32_t blocks_per_cu;  /* persistent grid = compute units x this, default 8 */
+  uint32_t blocks_per_cu;  /* persistent grid = compute units x this (256-thread blocks), default 3 */
   uint32_t slot_margin;    /* cl_sample slots: 0 = mu + 8 sqrt(mu) + 24 (default); 1 = no margin (tests
                               of the overflow replay: about half of the lanes overflow) */
   uint32_t reserved;

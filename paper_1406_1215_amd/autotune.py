@@ -22,7 +22,7 @@ from . import clgen
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 BUDGETS = (64, 96, 128, 192, 256, 384, 512)
-BLOCKS_PER_CU = (4, 8, 16)
+BLOCKS_PER_CU = (2, 3, 4, 8)
 
 
 def size_bucket(total_edges: float) -> str:

@@ -23,7 +23,7 @@ namespace {
 
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kDefaultBudget = 192;
-constexpr uint32_t kDefaultBlocksPerCu = 8;
+constexpr uint32_t kDefaultBlocksPerCu = 3;
 constexpr int kPersistThreads = 256;
 static_assert(kPersistThreads == kLaneThreads, "the lane kernels stage output for 256 threads");
 

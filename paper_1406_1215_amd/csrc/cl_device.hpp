@@ -40,14 +40,19 @@ struct Block4 {
   uint32_t x0, x1, x2, x3;
 };
 
+// three-way exclusive or in one v_bitop3_b32 (truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                            const RoundKeys& rk) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
     const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
-    const uint32_t y0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ rk.k0[r];
-    const uint32_t y2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ rk.k1[r];
+    const uint32_t y0 = xor3(static_cast<uint32_t>(pb >> 32), c1, rk.k0[r]);
+    const uint32_t y2 = xor3(static_cast<uint32_t>(pa >> 32), c3, rk.k1[r]);
     c1 = static_cast<uint32_t>(pb);
     c3 = static_cast<uint32_t>(pa);
     c0 = y0;
@@ -59,10 +64,12 @@ __device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
 // 53-bit uniform in (0,1) from two 32-bit words (hi:lo): (2*(x >> 12) + 1) * 2^-53.
 // Formed exactly as (1 + k 2^-52) - (1 - 2^-53), k = x >> 12: the first term
 // is k placed in the mantissa of 1.0 and the subtraction is exact (Sterbenz).
+// The two words of 1 + k 2^-52 are funnel shifts: (hi:lo) >> 12 and
+// (0x3FF:hi) >> 12.
 __device__ __forceinline__ double unit53(uint32_t hi, uint32_t lo) {
-  const uint64_t x = (static_cast<uint64_t>(hi) << 32) | lo;
-  const uint64_t k = x >> 12;
-  const double one_k = __longlong_as_double(static_cast<long long>(k | 0x3FF0000000000000ull));
+  const uint32_t mlo = __builtin_amdgcn_alignbit(hi, lo, 12);
+  const uint32_t mhi = __builtin_amdgcn_alignbit(0x3FFu, hi, 12);
+  const double one_k = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(mhi) << 32) | mlo));
   return one_k - 0x1.fffffffffffffp-1;
 }
 
