@@ -398,40 +398,67 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
 }
 
 // --------------------------------------------------------------------------
-// heavy-segment starts b_k (one thread per heavy segment)
+// heavy-segment table (one thread per heavy segment).  The graph's fields
+// are read once per thread into registers (before any store), and the two
+// boundary searches of a segment advance in lockstep so that their loads
+// overlap.
 // --------------------------------------------------------------------------
+struct HeavyCtx {
+  uint64_t hs_off, H, r_off, SB0, u_begin, q_off, Qbase, Qn, n;
+};
+
+__device__ __forceinline__ HeavyCtx heavy_ctx(const GraphDesc& d) {
+  return HeavyCtx{d.hs_off, d.H, d.r_off, d.SB0, d.u_begin, d.q_off, d.Qbase, d.Qend - d.Qbase, d.n};
+}
+
 __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
   if (hdr->status) return;
   const GraphDesc* desc = hdr->desc;
   const uint32_t G = hdr->G;
   const uint64_t NH = hdr->total_nh;
+  const uint64_t* SB = hdr->SB;
+  const uint64_t* Q = hdr->Q;
+  HSeg* hseg = hdr->hseg;
+  const HeavyCtx c0 = heavy_ctx(desc[0]);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t h = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; h < NH; h += stride) {
-    const uint32_t g = find_graph(G, h, [&](uint32_t x) { return desc[x].hs_off; });
-    const GraphDesc& d = desc[g];
-    const uint64_t hl = h - d.hs_off;
+    const HeavyCtx c = (G == 1) ? c0 : heavy_ctx(desc[find_graph(G, h, [&](uint32_t x) { return desc[x].hs_off; })]);
+    const uint64_t hl = h - c.hs_off;
     // heavy source: last r in [0, H) with SB(r) - SB0 <= hl
-    uint64_t lo = 0, hi = d.H;
+    uint64_t lo = 0, hi = c.H;
     while (hi - lo > 1) {
       const uint64_t mid = (lo + hi) >> 1;
-      if (hdr->SB[d.r_off + mid] - d.SB0 <= hl) lo = mid; else hi = mid;
+      if (SB[c.r_off + mid] - c.SB0 <= hl) lo = mid; else hi = mid;
     }
     const uint64_t r = lo;
-    const uint64_t sb = hdr->SB[d.r_off + r] - d.SB0;
-    const uint64_t K = hdr->SB[d.r_off + r + 1] - hdr->SB[d.r_off + r];
-    const uint64_t k = hl - sb;
-    const uint64_t u = d.u_begin + r;
-    const uint64_t base = hdr->Q[d.q_off + u + 1] - d.Qbase;
-    const uint64_t Dm = (d.Qend - d.Qbase) - base;
-    // b_kk: first candidate of segment kk (b_0 = u + 1; the last segment ends at n)
-    auto bound = [&](uint64_t kk) -> uint64_t {
-      if (kk == 0) return u + 1;
-      if (kk >= K) return d.n;
-      const uint64_t target = kk * (Dm / K) + (kk * (Dm % K)) / K;
-      return q_lower_bound(hdr->Q, d.q_off, d.Qbase, u + 1, d.n, base + target);
-    };
-    hdr->hseg[h] = HSeg{static_cast<uint32_t>(u), static_cast<uint32_t>(k), static_cast<uint32_t>(bound(k)),
-                        static_cast<uint32_t>(bound(k + 1))};
+    const uint64_t sbr = SB[c.r_off + r];
+    const uint64_t K = SB[c.r_off + r + 1] - sbr;
+    const uint64_t k = hl - (sbr - c.SB0);
+    const uint64_t u = c.u_begin + r;
+    const uint64_t* Qg = Q + c.q_off;
+    const uint64_t base = Qg[u + 1] - c.Qbase;
+    const uint64_t Dm = c.Qn - base;
+    // b_kk = first v in [u+1, n] with Q_v - Q_{u+1} >= kk floor(D/K) + floor(kk (D mod K) / K)
+    // (b_0 = u + 1; the last segment ends at n)
+    auto target = [&](uint64_t kk) { return base + kk * (Dm / K) + (kk * (Dm % K)) / K; };
+    const uint64_t t0 = target(k), t1 = target(k + 1);
+    uint64_t lo0 = u + 1, hi0 = c.n, lo1 = u + 1, hi1 = c.n;
+    if (k == 0) hi0 = lo0;
+    if (k + 1 >= K) lo1 = hi1;
+    while (lo0 < hi0 || lo1 < hi1) {
+      const uint64_t m0 = lo0 + ((hi0 - lo0) >> 1);
+      const uint64_t m1 = lo1 + ((hi1 - lo1) >> 1);
+      const uint64_t q0 = (lo0 < hi0) ? Qg[m0] - c.Qbase : 0;
+      const uint64_t q1 = (lo1 < hi1) ? Qg[m1] - c.Qbase : 0;
+      if (lo0 < hi0) {
+        if (q0 >= t0) hi0 = m0; else lo0 = m0 + 1;
+      }
+      if (lo1 < hi1) {
+        if (q1 >= t1) hi1 = m1; else lo1 = m1 + 1;
+      }
+    }
+    hseg[h] = HSeg{static_cast<uint32_t>(u), static_cast<uint32_t>(k), static_cast<uint32_t>(lo0),
+                   static_cast<uint32_t>(lo1)};
   }
 }
 
@@ -444,25 +471,40 @@ __device__ __forceinline__ uint64_t lane_floor(uint64_t C, uint64_t L, uint64_t 
   return static_cast<uint64_t>(floor(static_cast<double>(C) * static_cast<double>(L) / static_cast<double>(Z)));
 }
 
+struct PlanCtx {
+  const double* w;
+  double S;
+  uint64_t r_off, nr, u_begin, L, Z, C0, SB0, lane_off;
+};
+
+__device__ __forceinline__ PlanCtx plan_ctx(const GraphDesc& d) {
+  return PlanCtx{d.w, d.S, d.r_off, d.u_end - d.u_begin, d.u_begin, d.L, d.C1 - d.C0, d.C0, d.SB0, d.lane_off};
+}
+
 __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
   if (hdr->status) return;
   const GraphDesc* desc = hdr->desc;
   const uint32_t G = hdr->G;
   const uint64_t total_r = hdr->total_r;
+  const uint64_t* C = hdr->C;
+  const uint64_t* SB = hdr->SB;
+  double* A = hdr->A;
+  uint32_t* lane_seg = hdr->lane_seg;
+  uint64_t* lane_cum = hdr->lane_cum;
+  const PlanCtx c0 = plan_ctx(desc[0]);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total_r; i += stride) {
-    const uint32_t g = find_graph(G, i, [&](uint32_t x) { return desc[x].r_off; });
-    const GraphDesc& d = desc[g];
+    const PlanCtx d = (G == 1) ? c0 : plan_ctx(desc[find_graph(G, i, [&](uint32_t x) { return desc[x].r_off; })]);
     const uint64_t r = i - d.r_off;
-    const uint64_t nr = d.u_end - d.u_begin;
-    if (r >= nr) continue;
-    hdr->A[i] = d.w[d.u_begin + r] / d.S;  // a_u of Alg. 1, once per source
+    if (r >= d.nr) continue;
+    A[i] = d.w[d.u_begin + r] / d.S;  // a_u of Alg. 1, once per source
     if (d.L == 0) continue;
     const uint64_t L = d.L;
-    const uint64_t Z = d.C1 - d.C0;
-    const uint64_t cex = hdr->C[i] - d.C0;
-    const uint64_t cin = hdr->C[i + 1] - d.C0;
-    const uint64_t K = hdr->SB[i + 1] - hdr->SB[i];
+    const uint64_t Z = d.Z;
+    const uint64_t cex = C[i] - d.C0;
+    const uint64_t cin = C[i + 1] - d.C0;
+    const uint64_t sbi = SB[i];
+    const uint64_t K = SB[i + 1] - sbi;
     uint64_t ilo = (r == 0) ? 0 : lane_floor(cex, L, Z) + 1;
     uint64_t ihi = lane_floor(cin, L, Z);
     if (ihi > L - 1) ihi = L - 1;
@@ -472,13 +514,13 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
       double kk = ceil((Ti - static_cast<double>(cex)) * static_cast<double>(K) / cnode) - 1.0;
       if (!(kk > 0.0)) kk = 0.0;
       if (kk > static_cast<double>(K - 1)) kk = static_cast<double>(K - 1);
-      hdr->lane_seg[d.lane_off + li] = static_cast<uint32_t>(hdr->SB[i] - d.SB0 + static_cast<uint64_t>(kk));
-      if (hdr->lane_cum) {
+      lane_seg[d.lane_off + li] = static_cast<uint32_t>(sbi - d.SB0 + static_cast<uint64_t>(kk));
+      if (lane_cum) {
         // plan cost before the lane's first segment (segments of a source share its cost equally)
         const double before = static_cast<double>(cex) + kk * cnode / static_cast<double>(K);
         uint64_t cb = static_cast<uint64_t>(before);
         if (cb > cin) cb = cin;
-        hdr->lane_cum[d.lane_off + li] = cb;
+        lane_cum[d.lane_off + li] = cb;
       }
     }
   }
@@ -930,7 +972,7 @@ __global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out
   const int lane = threadIdx.x & 63;
   const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (blockDim.x / 64);
   gptr<uint64_t> slots = to_global(uniptr(reinterpret_cast<const uint64_t*>(hdr->slots)));
-  uint64_t* out64 = reinterpret_cast<uint64_t*>(out);
+  const gout<uint64_t> out64 = to_global_mut(uniptr_mut(reinterpret_cast<uint64_t*>(out)));
   for (uint64_t grp = uni64(static_cast<uint64_t>(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6));
        grp < ngroups; grp += nwaves) {
     const uint64_t l = grp * kLaneGroup + lane;
@@ -946,7 +988,20 @@ __global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out
       if (cnt == 0 || cnt > cap || pos >= hi || pos + cnt <= lo) continue;
       const uint64_t a = (pos > lo) ? pos : lo;
       const uint64_t b = (pos + cnt < hi) ? pos + cnt : hi;
-      for (uint64_t e = a + lane; e < b; e += 64) out64[e - lo] = slots[s0 + (e - pos)];
+      // 256 edges per step: four independent loads in flight per lane
+      for (uint64_t e0 = a; e0 < b; e0 += 256) {
+        uint64_t x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint64_t e = e0 + r * 64 + lane;
+          if (e < b) x[r] = slots[s0 + (e - pos)];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint64_t e = e0 + r * 64 + lane;
+          if (e < b) out64[e - lo] = x[r];
+        }
+      }
     }
   }
 }
