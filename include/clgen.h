@@ -157,6 +157,20 @@ cl_status cl_sample(const cl_graph* g /* host, G entries */, uint32_t G, const c
 cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t edge_begin, uint64_t cap,
                       uint64_t* graph_offsets, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Degrees of the planned graphs without storing any edge (the generator's
+ * output analysed on the fly, Sec. 5 "generate and analyse without I/O"):
+ * runs the planned lanes once more with the same random words and adds, for
+ * every kept edge (u, v), 1 to deg[q_g + u] and deg[q_g + v], where
+ * q_g = sum over earlier tasks h of (n_h + 1) (for one task, deg[0 .. n)).
+ * Adds into deg (the caller zeroes it, so that several plans, e.g. the parts
+ * of a partition, can accumulate into one array).  deg: device uint32,
+ * deg_len >= sum_g (n_g + 1), else CL_ERR_CAPACITY.  ws must hold a plan of
+ * cl_count or cl_sample.  Synchronises once (reads the plan's sizes), then
+ * launches asynchronously.
+ * ------------------------------------------------------------------------- */
+cl_status cl_degrees(void* ws, const cl_tuning* t, uint32_t* deg, uint64_t deg_len, void* stream);
+
 /* Totals of the plan in ws (host outputs, each may be NULL; synchronises).
  * lanes includes the padding to whole wavefronts; candidates is the number of
  * candidates the lane kernel visited (the "edges + sources" work of Eq. 2-4,

@@ -76,6 +76,7 @@ def lib():
         "cl_plan_info": (S, [_P, _U64P, _U64P, _U64P, _U64P, ctypes.POINTER(ctypes.c_float),
                               ctypes.POINTER(ctypes.c_uint32), _P]),
         "cl_hash_edges": (S, [_P, _U64, _U64, _P, _P]),
+        "cl_degrees": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _P]),
         "cl_batch_capture": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _P, _U64,
                                  _P, ctypes.POINTER(ctypes.c_void_p), _P]),
         "cl_batch_launch": (S, [_P, _P]),
@@ -257,6 +258,25 @@ def cl_generate(plan: Plan, edges: Optional[torch.Tensor] = None, edge_begin: in
     _check(L.cl_generate(_ptr(plan.ws), _tuning(plan.tuning), _ptr(edges), int(edge_begin), int(cap),
                          _ptr(graph_offsets), _stream(stream)), "cl_generate")
     return edges[: int(cap)]
+
+
+def cl_degrees(plan: Plan, deg: Optional[torch.Tensor] = None, stream=None) -> List[torch.Tensor]:
+    """Degrees of the planned graphs without storing edges: adds into `deg`
+    (an int32 tensor holding uint32 counts, sum(n_g + 1) entries; created
+    zeroed when None) and returns one view of n_g entries per task."""
+    L = lib()
+    sizes = [int(t.w.numel()) for t in plan.tasks]
+    total = sum(n + 1 for n in sizes)
+    if deg is None:
+        deg = torch.zeros(max(total, 1), dtype=torch.int32, device=plan.ws.device)
+    assert deg.dtype == torch.int32 and deg.is_contiguous()
+    _check(L.cl_degrees(_ptr(plan.ws), _tuning(plan.tuning), _ptr(deg), int(deg.numel()), _stream(stream)),
+           "cl_degrees")
+    out, off = [], 0
+    for n in sizes:
+        out.append(deg[off: off + n])
+        off += n + 1
+    return out
 
 
 def cl_plan_info(plan_or_ws, stream=None) -> dict:

@@ -206,12 +206,12 @@ hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* 
     hipLaunchKernelGGL(k_slot_check, dim3(1), dim3(1), 0, s, dhdr);
     if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL((k_lanes<2>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                       static_cast<uint2*>(nullptr), 0ull, 0ull);
+                       static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr));
     if (ev1) (void)hipEventRecord(ev1, s);
   } else {
     if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL((k_lanes<0>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                       static_cast<uint2*>(nullptr), 0ull, 0ull);
+                       static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr));
     if (ev1) (void)hipEventRecord(ev1, s);
   }
   hipError_t e = device_scan<uint64_t>(CntIn{{}, h.lane_cnt, h.cap_nl}, OffOut{{}, h.lane_pos}, h.cap_nl + 1,
@@ -231,7 +231,7 @@ hipError_t launch_write(WsHeader* dhdr, const cl_tuning* t, uint32_t* edges, uin
   hipLaunchKernelGGL(k_compact, dim3(cus * 16), dim3(256), 0, s, dhdr, reinterpret_cast<uint2*>(edges), lo, hi);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
   hipLaunchKernelGGL((k_lanes<1>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                     reinterpret_cast<uint2*>(edges), lo, hi);
+                     reinterpret_cast<uint2*>(edges), lo, hi, static_cast<uint32_t*>(nullptr));
   if (graph_offsets) hipLaunchKernelGGL(k_graph_offsets, dim3(16), dim3(256), 0, s, dhdr, graph_offsets);
   return hipGetLastError();
 }
@@ -546,6 +546,23 @@ cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t ed
   // G for the offsets kernel: read from the header (the launch covers up to 2^20 tasks)
   CL_TRY(launch_write(dhdr, t, edges, edge_begin, edge_begin + cap, graph_offsets, s));
   return CL_OK;
+}
+
+cl_status cl_degrees(void* ws, const cl_tuning* t, uint32_t* deg, uint64_t deg_len, void* stream) {
+  if (!ws || !deg) return CL_ERR_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  WsHeader* dhdr = static_cast<WsHeader*>(ws);
+  WsHeader back{};
+  CL_TRY(hipMemcpyAsync(&back, ws, sizeof(back), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipStreamSynchronize(s));
+  if (back.magic != kWsMagic) return CL_ERR_NOT_PLANNED;
+  if (back.status) return status_error(back.status);
+  if (!back.planned) return CL_ERR_NOT_PLANNED;
+  if (deg_len < back.total_q) return CL_ERR_CAPACITY;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
+  hipLaunchKernelGGL((k_lanes<3>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
+                     static_cast<uint2*>(nullptr), 0ull, 0ull, deg);
+  return hip_status(hipGetLastError());
 }
 
 cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments, uint64_t* edges,

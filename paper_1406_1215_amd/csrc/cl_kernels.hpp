@@ -767,9 +767,35 @@ struct SlotEmit {
   }
 };
 
+// Degree consumer: every kept edge (u, v) adds 1 to the degrees of u and v,
+// and no edge is stored.  The source's count is kept in a register and added
+// once per run of equal u; integer additions commute, so the result does not
+// depend on the schedule.
+struct DegEmit {
+  uint32_t* deg;      // degrees of the bound graph's nodes
+  uint32_t cur, cnt;  // source whose edges are being counted, and how many so far
+  __device__ void flush() {
+    if (cnt) atomicAdd(&deg[cur], cnt);
+    cnt = 0;
+  }
+  __device__ bool operator()(uint32_t u, uint32_t v) {
+    atomicAdd(&deg[v], 1u);
+    if (u != cur) {
+      flush();
+      cur = u;
+    }
+    ++cnt;
+    return true;
+  }
+};
+
 template <int kMode>
 struct EmitOf {
   using type = SlotEmit;
+};
+template <>
+struct EmitOf<3> {
+  using type = DegEmit;
 };
 template <>
 struct EmitOf<0> {
@@ -782,7 +808,8 @@ struct EmitOf<1> {
 
 // The lane kernel.  kMode 0: count pass.  kMode 1: write pass (replay into
 // the output window; in one-pass plans only the units that overflowed their
-// slot).  kMode 2: one pass, count and write into slots.
+// slot).  kMode 2: one pass, count and write into slots.  kMode 3: degrees
+// only (adds into deg at each graph's node offset q_off; no edge output).
 //
 // Scheduling: the work units of the lane plan (Eq. 5 applied to lanes) are
 // handed out dynamically.  A wavefront takes chunks of 64 consecutive units
@@ -792,13 +819,14 @@ struct EmitOf<1> {
 // wavefront work on one graph at a time (its parameters live in scalar
 // registers); a chunk of another graph is handed out once every lane is idle.
 template <int kMode>
-__global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* out, uint64_t e_lo, uint64_t e_hi) {
+__global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* out, uint64_t e_lo, uint64_t e_hi,
+                                                       uint32_t* deg) {
   using Emit = typename EmitOf<kMode>::type;
-  constexpr bool kWrite = (kMode != 0);
+  constexpr bool kWrite = (kMode == 1 || kMode == 2);
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   __shared__ uint2 stage[kWrite ? kStageSlots * kLaneThreads : 1];
   if (hdr->status || hdr->magic != kWsMagic) return;
-  if (kMode == 1 && !hdr->planned) return;
+  if ((kMode == 1 || kMode == 3) && !hdr->planned) return;
   const bool only_overflow = (kMode == 1) && (uni32(hdr->mode) == 1);
   if (only_overflow && uni32(hdr->overflow) == 0) return;
   const GraphDesc* desc = hdr->desc;
@@ -821,6 +849,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
   RoundKeys rk{};
   uint64_t unit_end = 0;     // one past the graph's last (padded) unit
   uint32_t nseg = 0;         // segments of the graph
+  uint32_t* degp = nullptr;  // degree mode: the graph's degree array
   uint32_t cnext = 0, cend = 0, cgraph = kNone;
   bool queue_done = false;
 
@@ -844,6 +873,8 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
         em.wr.finish();
         lane_cnt[unit] = em.c;
         if (em.over) atomicAdd(overflow, 1u);
+      } else if constexpr (kMode == 3) {
+        em.flush();
       } else {
         if (touched) em.finish();
       }
@@ -878,6 +909,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
           rk = philox_round_keys(uni64(d.seed));
           unit_end = uni64(d.lane_off) + uni64(d.NL);
           nseg = uni32(static_cast<uint32_t>(d.SB1 - d.SB0));
+          if constexpr (kMode == 3) degp = uniptr_mut(deg) + uni64(d.q_off);
         }
         // rank of this lane among the idle lanes
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(idle_mask >> 32),
@@ -896,6 +928,8 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
             em.wr = WriteEmit{stage, slots, 0ull, s0, s1, 0u};
             em.c = 0u;
             em.over = false;
+          } else if constexpr (kMode == 3) {
+            em = DegEmit{degp, kNone, 0u};
           } else {
             const uint64_t pos0 = lane_pos[unit];
             const uint64_t cnt = lane_cnt[unit];
@@ -915,7 +949,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
     // (4) one candidate step
     if (s.inseg) candidate_step(s, cx, rk, sr, em, visits);
   }
-  if (kMode != 1) {
+  if (kMode == 0 || kMode == 2) {
     // candidates visited by the wavefront (statistics of the cost model)
     uint64_t visited = visits;
     for (int dd = 32; dd >= 1; dd >>= 1) visited += shfl_idx64(visited, lane ^ dd);

@@ -19,7 +19,7 @@ def test_header_declares_the_boundary():
     names = _declared()
     for want in ["cl_weight_sum", "cl_expected_edges", "cl_partition", "cl_count", "cl_generate",
                  "cl_expected_degree", "cl_expected_degree_backward", "cl_batch_capture", "cl_batch_launch",
-                 "cl_hash_edges"]:
+                 "cl_hash_edges", "cl_degrees"]:
         assert want in names
 
 

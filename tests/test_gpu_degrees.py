@@ -1,0 +1,86 @@
+"""GPU: degrees of generated graphs without storing edges (cl_degrees),
+against the degree counts of the oracle's edge lists, bit-exact."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1406_1215_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PLANNERS = ["cl_count", "cl_sample"]
+
+
+@pytest.fixture(scope="module")
+def cg():
+    from conftest import gpu_available
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_1406_1215_amd import clgen
+    clgen.lib()
+    return clgen
+
+
+def _dev(w):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(w, dtype=np.float64)).to("cuda:0")
+
+
+def _oracle_degrees(w, S, seed, u0=0, u1=None):
+    edges, m, _, _ = O.generate(w, S, seed, u0, u1)
+    return np.bincount(edges.ravel().astype(np.int64), minlength=w.size).astype(np.int64), m
+
+
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_degrees_small_config(cg, planner):
+    w = W.config_small()
+    S = O.exact_sum(w)
+    want, m = _oracle_degrees(w, S, 1)
+    plan = getattr(cg, planner)([cg.Task(_dev(w), S, 1)])
+    (deg,) = cg.cl_degrees(plan)
+    got = deg.cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(got, want)
+    assert got.sum() == 2 * m == 2 * plan.total
+
+
+@pytest.mark.parametrize("n", [100_000, 1_000_000])
+def test_degrees_plain_shapes_and_ranges(cg, n):
+    w = W.config_plain(n=n)
+    S = O.exact_sum(w)
+    want, m = _oracle_degrees(w, S, 7)
+    plan = cg.cl_sample([cg.Task(_dev(w), S, 7)])
+    (deg,) = cg.cl_degrees(plan)
+    assert np.array_equal(deg.cpu().numpy().view(np.uint32).astype(np.int64), want)
+    # the parts of a partition accumulate into one array: same degrees
+    bounds, _ = cg.cl_partition(_dev(w), S, 3)
+    import torch
+    acc = torch.zeros(n + 1, dtype=torch.int32, device="cuda:0")
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        part = cg.cl_count([cg.Task(_dev(w), S, 7, a, b)])
+        cg.cl_degrees(part, deg=acc)
+    assert np.array_equal(acc[:n].cpu().numpy().view(np.uint32).astype(np.int64), want)
+
+
+def test_degrees_batch_of_uneven_graphs(cg):
+    rng = np.random.default_rng(21)
+    ws = [W.powerlaw_capped(int(n), a, 2.0, np.random.default_rng(int(n)))
+          for n, a in zip(rng.integers(1, 30000, 6), rng.uniform(2.0, 3.0, 6))]
+    ws.append(np.zeros(4))
+    tasks, wants = [], []
+    for i, w in enumerate(ws):
+        S = O.exact_sum(w) if w.sum() > 0 else 1.0
+        wants.append(_oracle_degrees(w, S, 100 + i)[0])
+        tasks.append(cg.Task(_dev(w), S, 100 + i))
+    plan = cg.cl_sample(tasks)
+    degs = cg.cl_degrees(plan)
+    for d, want in zip(degs, wants):
+        assert np.array_equal(d.cpu().numpy().view(np.uint32).astype(np.int64), want)
+
+
+def test_degrees_capacity_error(cg):
+    import torch
+    w = W.config_small(n=2000)
+    S = O.exact_sum(w)
+    plan = cg.cl_count([cg.Task(_dev(w), S, 1)])
+    with pytest.raises(cg.ClError):
+        cg.cl_degrees(plan, deg=torch.zeros(100, dtype=torch.int32, device="cuda:0"))
