@@ -21,6 +21,9 @@ writing), offsets, compaction of the slots into the contiguous edge list.
 * hbm_write: bytes of edges written per second by that kernel and by the
   compaction copy, against 8 TB/s;
 * two_pass: the count-then-replay path (count pass, offsets, write pass);
+* partition_ablation: generation-kernel time with work units of equal
+  expected cost (Eq. 5) vs units of equal source counts (Sec. 4's naive
+  consecutive partition), same number of units;
 * batched: 256 uneven graphs in one captured HIP graph vs 256 plain calls;
 * cpu_baseline: the CPU oracle on a bounded sample of the same workload.
 """
@@ -75,6 +78,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-two-pass", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000, help="sources of the plain workload")
     ap.add_argument("--verbose", action="store_true")
@@ -207,6 +211,9 @@ def main():
     if not args.no_two_pass:
         result["two_pass"] = bench_two_pass(args, cg, torch, w, seed, dev, stream)
 
+    if not args.no_ablation:
+        result["partition_ablation"] = bench_partition(cg, torch, w, seed)
+
     if not args.no_batched:
         result["batched"] = bench_batched(args, cg, W, torch, np, dev)
 
@@ -230,6 +237,26 @@ def main():
         result["cpu_baseline"] = bench_cpu(w_np, seed)
 
     print(json.dumps(result), flush=True)
+
+
+def bench_partition(cg, torch, w, seed):
+    """Sec. 4's comparison on one GPU: work units of equal expected cost
+    (Eq. 5 applied to lanes) vs units of equal numbers of sources, same unit
+    count; generation-kernel time of each (same output)."""
+    S = cg.cl_weight_sum(w)
+    out = {}
+    for name, pol in (("equal_cost_ms", 0), ("equal_sources_ms", 1)):
+        plan = None
+        ms = []
+        for _ in range(3):
+            plan = cg.cl_sample([cg.Task(w, S, seed)], tuning={"partition": pol},
+                                ws=plan.ws if plan is not None else None)
+            ms.append(cg.cl_plan_info(plan)["lane_kernel_ms"])
+        out[name] = min(ms)
+        out["edges"] = plan.total
+        del plan
+    out["slowdown_equal_sources"] = out["equal_sources_ms"] / out["equal_cost_ms"]
+    return out
 
 
 def bench_two_pass(args, cg, torch, w, seed, dev, stream):

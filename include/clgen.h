@@ -72,7 +72,9 @@ typedef struct cl_tuning {
   uint32_t blocks_per_cu;  /* persistent grid = compute units x this (256-thread blocks), default 3 */
   uint32_t slot_margin;    /* cl_sample slots: 0 = mu + 8 sqrt(mu) + 24 (default); 1 = no margin (tests
                               of the overflow replay: about half of the lanes overflow) */
-  uint32_t reserved;
+  uint32_t partition;      /* work units: 0 = equal expected cost (Eq. 5 applied to lanes, default);
+                              1 = equal numbers of sources (the naive consecutive partition Sec. 4
+                              compares against; heavy sources then serialise their unit) */
 } cl_tuning;
 
 /* ---------------------------------------------------------------------------

@@ -437,6 +437,7 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
     d.q_off = qo;
     d.r_off = ro;
     d.budget = bu;
+    d.policy = (t && t->partition == 1) ? 1u : 0u;
     qo += g[i].n + 1;
     ro += (g[i].u_end - g[i].u_begin) + 1;
     desc[i] = d;

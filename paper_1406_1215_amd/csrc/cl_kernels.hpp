@@ -366,6 +366,7 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
       if (nr > 0 && d.qscale != 0.0 && d.status == 0) {
         L = (Z + d.budget - 1) / d.budget;
         if (L > nseg) L = nseg;
+        if (d.policy == 1 && L > nr) L = nr;   // equal source counts: at most one unit per source
         if (L == 0) L = 1;
       }
       d.L = L;
@@ -475,10 +476,12 @@ struct PlanCtx {
   const double* w;
   double S;
   uint64_t r_off, nr, u_begin, L, Z, C0, SB0, lane_off;
+  uint32_t policy;
 };
 
 __device__ __forceinline__ PlanCtx plan_ctx(const GraphDesc& d) {
-  return PlanCtx{d.w, d.S, d.r_off, d.u_end - d.u_begin, d.u_begin, d.L, d.C1 - d.C0, d.C0, d.SB0, d.lane_off};
+  return PlanCtx{d.w, d.S, d.r_off, d.u_end - d.u_begin, d.u_begin, d.L, d.C1 - d.C0, d.C0, d.SB0, d.lane_off,
+                 d.policy};
 }
 
 __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
@@ -505,6 +508,16 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
     const uint64_t cin = C[i + 1] - d.C0;
     const uint64_t sbi = SB[i];
     const uint64_t K = SB[i + 1] - sbi;
+    if (d.policy == 1) {
+      // equal source counts: unit li starts at source floor(li nr / L), segment 0
+      // (L <= nr, so a source starts at most one unit)
+      const uint64_t li = (r * L + d.nr - 1) / d.nr;          // ceil(r L / nr)
+      if (li < L && (li * d.nr) / L == r) {
+        lane_seg[d.lane_off + li] = static_cast<uint32_t>(sbi - d.SB0);
+        if (lane_cum) lane_cum[d.lane_off + li] = cex;
+      }
+      continue;
+    }
     uint64_t ilo = (r == 0) ? 0 : lane_floor(cex, L, Z) + 1;
     uint64_t ihi = lane_floor(cin, L, Z);
     if (ihi > L - 1) ihi = L - 1;

@@ -43,7 +43,7 @@ struct GraphDesc {
   uint64_t m;        // edges
   uint64_t edge_off; // first edge in the batch output
   uint32_t status;
-  uint32_t pad;
+  uint32_t policy;   // host: 0 = units of equal cost, 1 = units of equal source counts
 };
 
 struct Triple {

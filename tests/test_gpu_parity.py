@@ -124,7 +124,9 @@ def test_source_ranges_bit_exact(planner, cg, u0, u1):
 
 
 @pytest.mark.parametrize("tuning", [{"lane_budget": 1}, {"lane_budget": 17}, {"lane_budget": 4096},
-                                    {"lane_budget": 192, "blocks_per_cu": 1}, {"blocks_per_cu": 32}])
+                                    {"lane_budget": 192, "blocks_per_cu": 1}, {"blocks_per_cu": 32},
+                                    {"partition": 1}, {"partition": 1, "lane_budget": 1},
+                                    {"partition": 1, "lane_budget": 1 << 20}])
 @pytest.mark.parametrize("planner", PLANNERS)
 def test_schedule_does_not_change_output(planner, cg, tuning):
     w = _heavy(30000, 60, 40.0)
