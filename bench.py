@@ -79,6 +79,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-two-pass", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--full-graph-degrees", action="store_true",
+                    help="instead of the step: the degree sequence of the whole n=1e9 graph (exponent 2.1, mean "
+                         "degree 500), every edge generated and consumed on the fly, part by part")
+    ap.add_argument("--parts", type=int, default=64)
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000, help="sources of the plain workload")
     ap.add_argument("--verbose", action="store_true")
@@ -108,6 +112,9 @@ def main():
     cg.lib()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if args.full_graph_degrees:
+        print(json.dumps(bench_full_graph(args, cg, W, torch, np, dev)), flush=True)
+        return
 
     log("bench: generating the n=1e7 workload")
     w_np = W.config_plain(n=args.n)
@@ -237,6 +244,32 @@ def main():
         result["cpu_baseline"] = bench_cpu(w_np, seed)
 
     print(json.dumps(result), flush=True)
+
+
+def bench_full_graph(args, cg, W, torch, np, dev):
+    """The paper's largest power-law shape (1e9 nodes, mean degree 500) on one
+    GPU: all edges generated part by part (uniform consecutive partition) and
+    reduced to the degree sequence; checked against E[m] and Var[m]."""
+    from paper_1406_1215_amd import parts
+    log("bench: generating the n=1e9 weights")
+    w_np = W.config_share()
+    w = torch.from_numpy(w_np).to(dev)
+    del w_np
+    S = cg.cl_weight_sum(w)
+    Em, Vm = cg.cl_expected_edges(w, S)
+    log(f"bench: S = {S:.6g}, E[m] = {Em:.6g}; {args.parts} parts")
+    seed = 3
+    parts.degrees(w[: 1 << 20].contiguous(), float(w[: 1 << 20].sum().item()), seed, 2)   # warm-up (small)
+    res = parts.degrees(w, S, seed, args.parts, log=log if args.verbose else None)
+    m = res["edges"]
+    z = (m - Em) / math.sqrt(Vm)
+    deg = res["deg"]
+    return {"metric": "edges/sec generated and reduced to degrees, whole graph", "value": m / res["seconds"],
+            "unit": "edges/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f64",
+            "config": {"workload": "power law, n=1e9, exponent 2.1, mean degree 500, cap sqrt(500 n), Philox seed 3",
+                       "parts": args.parts},
+            "edges": m, "seconds": res["seconds"], "expected_edges": Em, "z_score_of_m": z,
+            "max_degree": int(deg.max().item()), "isolated_nodes": int((deg == 0).sum().item())}
 
 
 def bench_partition(cg, torch, w, seed):

@@ -160,6 +160,15 @@ cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t ed
                       uint64_t* graph_offsets, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The plan alone (validation, quantised prefix, segments, lane plan), without
+ * running the lanes: for cl_degrees, which needs no counts.  ws as for
+ * cl_count (cl_workspace_size with one_pass = 0 bounds it).  cl_generate on
+ * such a workspace writes nothing.  Synchronises twice.
+ * ------------------------------------------------------------------------- */
+cl_status cl_plan(const cl_graph* g /* host, G entries */, uint32_t G, const cl_tuning* t, void* ws,
+                  uint64_t ws_bytes, uint64_t* ws_required /* host, may be NULL */, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Degrees of the planned graphs without storing any edge (the generator's
  * output analysed on the fly, Sec. 5 "generate and analyse without I/O"):
  * runs the planned lanes once more with the same random words and adds, for
@@ -168,8 +177,8 @@ cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t ed
  * Adds into deg (the caller zeroes it, so that several plans, e.g. the parts
  * of a partition, can accumulate into one array).  deg: device uint32,
  * deg_len >= sum_g (n_g + 1), else CL_ERR_CAPACITY.  ws must hold a plan of
- * cl_count or cl_sample.  Synchronises once (reads the plan's sizes), then
- * launches asynchronously.
+ * cl_count, cl_sample or cl_plan.  Synchronises once (reads the plan's
+ * sizes), then launches asynchronously.
  * ------------------------------------------------------------------------- */
 cl_status cl_degrees(void* ws, const cl_tuning* t, uint32_t* deg, uint64_t deg_len, void* stream);
 

@@ -77,6 +77,8 @@ def lib():
                               ctypes.POINTER(ctypes.c_uint32), _P]),
         "cl_hash_edges": (S, [_P, _U64, _U64, _P, _P]),
         "cl_degrees": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _P]),
+        "cl_plan": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _U64, _U64P,
+                        _P]),
         "cl_batch_capture": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _P, _U64,
                                  _P, ctypes.POINTER(ctypes.c_void_p), _P]),
         "cl_batch_launch": (S, [_P, _P]),
@@ -224,10 +226,16 @@ def _plan(fn_name: str, one_pass: int, tasks: Sequence[Task], tuning, ws, stream
     m = (ctypes.c_uint64 * G)()
     req = _U64(0)
     fn = getattr(L, fn_name)
-    code = fn(arr, G, tun, _ptr(ws), ws.numel(), m, ctypes.byref(req), _stream(stream))
-    if code == -6:
+    if fn_name == "cl_plan":   # no edge counts
+        call = lambda: fn(arr, G, tun, _ptr(ws), ws.numel(), ctypes.byref(req), _stream(stream))
+    else:
+        call = lambda: fn(arr, G, tun, _ptr(ws), ws.numel(), m, ctypes.byref(req), _stream(stream))
+    code = call()
+    for _ in range(2):   # a too small workspace: first the fixed part, then the data-dependent rest
+        if code != -6:
+            break
         ws = _ws(req.value, dev)
-        code = fn(arr, G, tun, _ptr(ws), ws.numel(), m, ctypes.byref(req), _stream(stream))
+        code = call()
     _check(code, fn_name)
     return Plan(ws=ws, graphs=arr, tasks=tasks, m=[int(x) for x in m], tuning=tuning)
 
@@ -243,6 +251,12 @@ def cl_sample(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional
     """Plans the tasks and generates them in one pass into per-lane slots of
     the workspace; cl_generate then copies the slots to the output."""
     return _plan("cl_sample", 1, tasks, tuning, ws, stream)
+
+
+def cl_plan(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional[torch.Tensor] = None,
+            stream=None) -> Plan:
+    """The plan alone (no lane kernel, no counts: plan.m is zeros), for cl_degrees."""
+    return _plan("cl_plan", 0, tasks, tuning, ws, stream)
 
 
 def cl_generate(plan: Plan, edges: Optional[torch.Tensor] = None, edge_begin: int = 0, cap: Optional[int] = None,

@@ -198,6 +198,11 @@ hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* 
   hipLaunchKernelGGL(k_lane_plan, dim3(grid_for(h.total_r, 256, cap)), dim3(256), 0, s, dhdr);
   hipLaunchKernelGGL(k_lane_groups, dim3(grid_for(h.cap_nl / kLaneGroup, 256, cap)), dim3(256), 0, s, dhdr);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
+  if (h.mode == 2) {   // plan only (cl_plan): no lane kernel, no counts
+    if (ev0) (void)hipEventRecord(ev0, s);
+    if (ev1) (void)hipEventRecord(ev1, s);
+    return hipGetLastError();
+  }
   if (h.mode == 1) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->overflow, 0u);
     hipError_t e = device_scan<uint64_t>(SlotIn{dhdr}, SlotOut{{}, h.slot_off}, h.cap_nl + 1,
@@ -515,15 +520,19 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
   if (eb == hipSuccess && hipMemcpyAsync(m_out, h.m_dev, 8ull * G, hipMemcpyDeviceToHost, s) == hipSuccess &&
       hipMemcpyAsync(&back, dhdr, sizeof(back), hipMemcpyDeviceToHost, s) == hipSuccess &&
       hipStreamSynchronize(s) == hipSuccess && ev0) {
-    if (hipEventElapsedTime(&lane_ms, ev0, ev1) != hipSuccess) lane_ms = -1.0f;
+    if (hipEventElapsedTime(&lane_ms, ev0, ev1) != hipSuccess) {
+      lane_ms = -1.0f;
+      (void)hipGetLastError();   // leave no error behind for the caller's next HIP call
+    }
   }
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
   if (eb != hipSuccess) return CL_ERR_DEVICE;
   if (back.status) return status_error(back.status);
-  const uint32_t one = 1;
+  // planned: 1 = counted (cl_count, cl_sample), 2 = plan only (cl_plan)
+  const uint32_t flag = (mode == 2) ? 2u : 1u;
   CL_TRY(hipMemcpyAsync(&dhdr->lane_ms, &lane_ms, sizeof(lane_ms), hipMemcpyHostToDevice, s));
-  CL_TRY(hipMemcpyAsync(&dhdr->planned, &one, sizeof(one), hipMemcpyHostToDevice, s));
+  CL_TRY(hipMemcpyAsync(&dhdr->planned, &flag, sizeof(flag), hipMemcpyHostToDevice, s));
   CL_TRY(hipStreamSynchronize(s));
   return CL_OK;
 }
@@ -536,6 +545,13 @@ cl_status cl_count(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, 
 cl_status cl_sample(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes, uint64_t* m_out,
                     uint64_t* ws_required, void* stream) {
   return plan_common(g, G, t, ws, ws_bytes, m_out, ws_required, stream, 1u);
+}
+
+cl_status cl_plan(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes,
+                  uint64_t* ws_required, void* stream) {
+  if (G == 0 || G > (1u << 24)) return CL_ERR_INVALID_ARG;
+  std::vector<uint64_t> m(G);
+  return plan_common(g, G, t, ws, ws_bytes, m.data(), ws_required, stream, 2u);
 }
 
 cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t edge_begin, uint64_t cap,

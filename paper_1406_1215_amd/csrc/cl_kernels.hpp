@@ -839,7 +839,8 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   __shared__ uint2 stage[kWrite ? kStageSlots * kLaneThreads : 1];
   if (hdr->status || hdr->magic != kWsMagic) return;
-  if ((kMode == 1 || kMode == 3) && !hdr->planned) return;
+  if (kMode == 1 && hdr->planned != 1) return;   // the write pass needs the counts
+  if (kMode == 3 && !hdr->planned) return;
   const bool only_overflow = (kMode == 1) && (uni32(hdr->mode) == 1);
   if (only_overflow && uni32(hdr->overflow) == 0) return;
   const GraphDesc* desc = hdr->desc;

@@ -8,7 +8,7 @@ from paper_1406_1215_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-PLANNERS = ["cl_count", "cl_sample"]
+PLANNERS = ["cl_count", "cl_sample", "cl_plan"]
 
 
 @pytest.fixture(scope="module")
@@ -40,7 +40,9 @@ def test_degrees_small_config(cg, planner):
     (deg,) = cg.cl_degrees(plan)
     got = deg.cpu().numpy().view(np.uint32).astype(np.int64)
     assert np.array_equal(got, want)
-    assert got.sum() == 2 * m == 2 * plan.total
+    assert got.sum() == 2 * m
+    if planner != "cl_plan":
+        assert plan.total == m
 
 
 @pytest.mark.parametrize("n", [100_000, 1_000_000])
@@ -56,7 +58,7 @@ def test_degrees_plain_shapes_and_ranges(cg, n):
     import torch
     acc = torch.zeros(n + 1, dtype=torch.int32, device="cuda:0")
     for a, b in zip(bounds[:-1], bounds[1:]):
-        part = cg.cl_count([cg.Task(_dev(w), S, 7, a, b)])
+        part = cg.cl_plan([cg.Task(_dev(w), S, 7, a, b)])
         cg.cl_degrees(part, deg=acc)
     assert np.array_equal(acc[:n].cpu().numpy().view(np.uint32).astype(np.int64), want)
 
@@ -84,3 +86,26 @@ def test_degrees_capacity_error(cg):
     plan = cg.cl_count([cg.Task(_dev(w), S, 1)])
     with pytest.raises(cg.ClError):
         cg.cl_degrees(plan, deg=torch.zeros(100, dtype=torch.int32, device="cuda:0"))
+
+
+def test_plan_only_workspace_writes_no_edges(cg):
+    import torch
+    w = W.config_small(n=3000)
+    S = O.exact_sum(w)
+    plan = cg.cl_plan([cg.Task(_dev(w), S, 2)])
+    out = torch.full((64, 2), -1, dtype=torch.int32, device="cuda:0")
+    cg.cl_generate(plan, edges=out, cap=64)
+    torch.cuda.synchronize()
+    assert bool((out == -1).all())
+
+
+def test_parts_give_the_whole_graph(cg):
+    """Degrees accumulated over a 5-part partition (parts.degrees) equal the
+    one-plan degrees and the degree counts of the oracle's edge list."""
+    from paper_1406_1215_amd import parts
+    w = W.config_plain(n=300_000)
+    S = O.exact_sum(w)
+    want, m = _oracle_degrees(w, S, 5)
+    res = parts.degrees(_dev(w), S, 5, parts=5)
+    assert res["edges"] == m
+    assert np.array_equal(res["deg"].cpu().numpy().view(np.uint32).astype(np.int64), want)
