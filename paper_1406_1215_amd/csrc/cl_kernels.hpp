@@ -369,6 +369,9 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
         if (d.policy == 1 && L > nr) L = nr;   // equal source counts: at most one unit per source
         if (L == 0) L = 1;
       }
+      // segment and unit indices are 32-bit: a graph above 2^32 - 1 segments
+      // is refused (n < 2^32 sources leaves room for ~1e9 heavy segments)
+      if (nseg > 0xFFFFFFFFull) atomicOr(&d.status, kStCapacity);
       d.L = L;
       d.NH = nh;
       cost = (L > 0) ? Z : 0;
@@ -394,6 +397,7 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
     uint32_t st = 0;
     for (uint32_t g = 0; g < G; ++g) st |= desc[g].status;
     if (hdr->cap_nl != 0 && (carry_nh > hdr->cap_nh || carry_nl > hdr->cap_nl)) st |= kStCapacity;
+    if (carry_nl > 0xFFFFFFFFull) st |= kStCapacity;   // units are numbered in 32 bits
     hdr->status |= st;
   }
 }
