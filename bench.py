@@ -21,6 +21,8 @@ writing), offsets, compaction of the slots into the contiguous edge list.
 * hbm_write: bytes of edges written per second by that kernel and by the
   compaction copy, against 8 TB/s;
 * two_pass: the count-then-replay path (count pass, offsets, write pass);
+* expected_degree: the float32 tiled expected-degree kernel and its adjoint
+  on n = 1e5 (1e10 pairs), against the VALU lane-operation peak;
 * partition_ablation: generation-kernel time with work units of equal
   expected cost (Eq. 5) vs units of equal source counts (Sec. 4's naive
   consecutive partition), same number of units;
@@ -79,6 +81,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-two-pass", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-expdeg", action="store_true")
     ap.add_argument("--full-graph-degrees", action="store_true",
                     help="instead of the step: the degree sequence of the whole n=1e9 graph (exponent 2.1, mean "
                          "degree 500), every edge generated and consumed on the fly, part by part")
@@ -221,6 +224,9 @@ def main():
     if not args.no_ablation:
         result["partition_ablation"] = bench_partition(cg, torch, w, seed)
 
+    if not args.no_expdeg:
+        result["expected_degree"] = bench_expdeg(cg, W, torch, dev)
+
     if not args.no_batched:
         result["batched"] = bench_batched(args, cg, W, torch, np, dev)
 
@@ -270,6 +276,36 @@ def bench_full_graph(args, cg, W, torch, np, dev):
                        "parts": args.parts},
             "edges": m, "seconds": res["seconds"], "expected_edges": Em, "z_score_of_m": z,
             "max_degree": int(deg.max().item()), "isolated_nodes": int((deg == 0).sum().item())}
+
+
+def bench_expdeg(cg, W, torch, dev, reps=5):
+    """Expected degree d_i = sum_{j != i} min(w_i w_j / S, 1) and its adjoint
+    on n = 1e5 float32 weights (1e10 pairs each), timed with events; ALU
+    work 3 lane-operations per pair forward (multiply, min, add) and 6
+    backward (multiply, compare, and a select and an add for each of the two
+    sums)."""
+    t = W.config_calib()
+    w32 = torch.from_numpy(t.astype("float32")).to(dev)
+    S = float(w32.double().sum().item())
+    n = w32.numel()
+    g = torch.randn(n, dtype=torch.float64, device=dev)
+    ws = cg._ed_ws(n, dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {"n": n, "pairs": n * n}
+    for name, fn, ops in (("forward", lambda: cg.cl_expected_degree(w32, S, ws=ws), 3),
+                          ("backward", lambda: cg.cl_expected_degree_backward(w32, S, g, True, ws=ws), 6)):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"{name}_ms"] = ms
+        out[f"{name}_pairs_per_s"] = n * n / (ms * 1e-3)
+        out[f"{name}_alu_frac"] = n * n * ops / (ms * 1e-3) / PEAK_LANE_OPS
+    return out
 
 
 def bench_partition(cg, torch, w, seed):
