@@ -42,7 +42,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 OPS_PER_CANDIDATE = 145          # operation count of one candidate step of the sampling rule
-PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 3.93e13 lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+# 7.86e13 lane-ops/s: the published fp32 vector peak (157.3 TFLOP/s) counts
+# an FMA as two flops, i.e. 128 lanes per CU per clock x 256 CUs x 2.4 GHz.
+# Without packed fp32 math an FMA issues at half this rate.
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
 BYTES_PER_CANDIDATE = 8           # w_v gathered
 BYTES_PER_EDGE = 8                # (u, v) uint32 pair written
 HBM_PEAK = 8.0e12                 # bytes/s
@@ -281,9 +284,10 @@ def bench_full_graph(args, cg, W, torch, np, dev):
 def bench_expdeg(cg, W, torch, dev, reps=5):
     """Expected degree d_i = sum_{j != i} min(w_i w_j / S, 1) and its adjoint
     on n = 1e5 float32 weights (1e10 pairs each), timed with events; ALU
-    work 3 lane-operations per pair forward (multiply, min, add) and 6
-    backward (multiply, compare, and a select and an add for each of the two
-    sums)."""
+    work 3 lane-operations per pair forward (multiply, min, add) and 3
+    backward (the clamped multiply-add that forms the mask, and one
+    multiply-add for each of the two sums; FMA-class, so at most half of
+    the lane-operation peak without packed math)."""
     t = W.config_calib()
     w32 = torch.from_numpy(t.astype("float32")).to(dev)
     S = float(w32.double().sum().item())
@@ -293,7 +297,7 @@ def bench_expdeg(cg, W, torch, dev, reps=5):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     out = {"n": n, "pairs": n * n}
     for name, fn, ops in (("forward", lambda: cg.cl_expected_degree(w32, S, ws=ws), 3),
-                          ("backward", lambda: cg.cl_expected_degree_backward(w32, S, g, True, ws=ws), 6)):
+                          ("backward", lambda: cg.cl_expected_degree_backward(w32, S, g, True, ws=ws), 3)):
         fn()
         torch.cuda.synchronize()
         e0.record()

@@ -658,15 +658,15 @@ cl_status cl_expected_degree_workspace(uint64_t n, uint64_t* bytes_out) {
   if (!bytes_out) return CL_ERR_INVALID_ARG;
   const uint64_t nt = (n + kEdCols - 1) / kEdCols;
   const uint64_t nb = (n + 255) / 256;
-  // a, gw (float n each), two float partial planes, A, B (double n), T partials
-  *bytes_out = 2 * align_up(4 * (n + 1)) + 2 * align_up(4 * nt * n + 4) + 2 * align_up(8 * (n + 1)) +
+  // a, thresholds, gw (float n each), two float partial planes, A, B (double n), T partials
+  *bytes_out = 3 * align_up(4 * (n + 1)) + 2 * align_up(4 * nt * n + 4) + 2 * align_up(8 * (n + 1)) +
                align_up(8 * (nb + 1)) + align_up(8);
   return CL_OK;
 }
 
 namespace {
 struct EdLayout {
-  float *a, *gw, *pA, *pB;
+  float *a, *thr, *gw, *pA, *pB;
   double *A, *B, *tp, *T;
   uint32_t nt, nb;
 };
@@ -678,6 +678,8 @@ EdLayout ed_layout(void* ws, uint64_t n) {
   const uint64_t nb = (n + 255) / 256;
   uint64_t off = 0;
   L.a = reinterpret_cast<float*>(base + off);
+  off += align_up(4 * (n + 1));
+  L.thr = reinterpret_cast<float*>(base + off);
   off += align_up(4 * (n + 1));
   L.gw = reinterpret_cast<float*>(base + off);
   off += align_up(4 * (n + 1));
@@ -710,7 +712,7 @@ cl_status cl_expected_degree(const float* w, uint64_t n, double S, double* d_out
   const EdLayout L = ed_layout(ws, n);
   const uint32_t nrow = static_cast<uint32_t>((n + kEdRows - 1) / kEdRows);
   hipLaunchKernelGGL(k_rowscale, dim3(L.nb), dim3(256), 0, s, w, n, S, L.a);
-  hipLaunchKernelGGL(k_expdeg_tile, dim3(nrow, L.nt), dim3(kEdRows), 0, s, w, L.a, n, L.pA);
+  hipLaunchKernelGGL(k_expdeg_tile, dim3(nrow, L.nt), dim3(kEdLanes), 0, s, w, L.a, n, L.pA);
   hipLaunchKernelGGL(k_expdeg_rows, dim3(L.nb), dim3(256), 0, s, w, L.a, n, L.nt, L.pA, d_out);
   return hip_status(hipGetLastError());
 }
@@ -727,8 +729,9 @@ cl_status cl_expected_degree_backward(const float* w, uint64_t n, double S, cons
   const EdLayout L = ed_layout(ws, n);
   const uint32_t nrow = static_cast<uint32_t>((n + kEdRows - 1) / kEdRows);
   hipLaunchKernelGGL(k_rowscale, dim3(L.nb), dim3(256), 0, s, w, n, S, L.a);
+  hipLaunchKernelGGL(k_threshold, dim3(L.nb), dim3(256), 0, s, L.a, n, L.thr);
   hipLaunchKernelGGL(k_gw, dim3(L.nb), dim3(256), 0, s, w, grad_d, n, L.gw);
-  hipLaunchKernelGGL(k_expdeg_bwd_tile, dim3(nrow, L.nt), dim3(kEdRows), 0, s, w, L.a, L.gw, n, L.pA, L.pB);
+  hipLaunchKernelGGL(k_expdeg_bwd_tile, dim3(nrow, L.nt), dim3(kEdLanes), 0, s, w, L.thr, L.gw, n, L.pA, L.pB);
   hipLaunchKernelGGL(k_expdeg_bwd_rows, dim3(L.nb), dim3(256), 0, s, w, L.a, grad_d, L.gw, n, L.nt, L.pA, L.pB, L.A,
                      L.B, L.tp);
   hipLaunchKernelGGL(k_sum_dbl, dim3(1), dim3(256), 0, s, L.tp, L.nb, L.T);

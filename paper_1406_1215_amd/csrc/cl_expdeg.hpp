@@ -3,11 +3,12 @@
 //   d_i = sum_{j != i} min(x_ij, 1),  x_ij = a_i w_j,  a_i = fl32(w_i / S)
 //
 // (Sec. 3 gives the uncapped form w_i - w_i^2/S.)  Tiles: a workgroup owns
-// kEdRows rows (one per lane) and one tile of kEdCols columns; the column
-// weights are wave-uniform, so they come through the scalar cache and each
-// pair costs three vector ops (multiply, min, add).  Every lane keeps four
-// float32 accumulators over the tile; tile partials are summed per row in
-// float64 by a second kernel, which also removes the j = i term.
+// kEdRows rows (kEdRowsPerLane per lane, kEdLanes lanes) and one tile of
+// kEdCols columns; the column weights are wave-uniform, so they come through
+// the scalar cache, sixteen at a time, and each pair costs three vector ops
+// (multiply, min, add).  Every row keeps four float32 accumulators over the
+// tile; tile partials are summed per row in float64 by a second kernel, which
+// also removes the j = i term.
 //
 // Adjoint, for g = dL/dd:
 //   dL/dw_k = (g_k A_k + B_k - T) / S,  A_k = sum_{j != k, x_kj < 1} w_j,
@@ -22,8 +23,11 @@
 
 namespace cl {
 
-constexpr int kEdRows = 256;
+constexpr int kEdLanes = 256;
+constexpr int kEdRowsPerLane = 2;
+constexpr int kEdRows = kEdLanes * kEdRowsPerLane;
 constexpr int kEdCols = 1024;
+constexpr int kEdUnroll = 16;
 
 __global__ void __launch_bounds__(256) k_rowscale(const float* __restrict__ w, uint64_t n, double S,
                                                   float* __restrict__ a) {
@@ -31,24 +35,66 @@ __global__ void __launch_bounds__(256) k_rowscale(const float* __restrict__ w, u
   if (i < n) a[i] = static_cast<float>(static_cast<double>(w[i]) / S);
 }
 
-// forward tile: part[tile * n + i] = sum_{j in tile} min(a_i w_j, 1) (float32)
-__global__ void __launch_bounds__(kEdRows) k_expdeg_tile(const float* __restrict__ w, const float* __restrict__ a,
-                                                         uint64_t n, float* __restrict__ part) {
-  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kEdRows + threadIdx.x;
+// Smallest float32 t with fl(a * t) >= 1.  Rounding is monotone in w, so for
+// every finite w >= 0 the capped test fl(a * w) < 1 holds exactly when w < t;
+// the adjoint tile then compares against t instead of forming the product.
+__device__ inline float cap_threshold(float a) {
+  if (!(a > 0.0f)) return __builtin_inff();
+  float t = 1.0f / a;
+  if (__builtin_isinf(t)) {
+    if (a * __FLT_MAX__ < 1.0f) return __builtin_inff();
+    t = __FLT_MAX__;
+  }
+  // a few ulps at most from the true boundary; walk to it
+  for (int it = 0; it < 64 && t > 0.0f && a * __uint_as_float(__float_as_uint(t) - 1u) >= 1.0f; ++it)
+    t = __uint_as_float(__float_as_uint(t) - 1u);
+  for (int it = 0; it < 64 && a * t < 1.0f; ++it) t = __uint_as_float(__float_as_uint(t) + 1u);
+  return t;
+}
+
+__global__ void __launch_bounds__(256) k_threshold(const float* __restrict__ a, uint64_t n, float* __restrict__ t) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = cap_threshold(a[i]);
+}
+
+// forward tile: part[tile * n + i] = sum_{j in tile} min(a_i w_j, 1) (float32).
+// Row i = blockIdx.x * kEdRows + r * kEdLanes + lane; column j of the tile
+// goes to accumulator j mod 4 of every row.
+__global__ void __launch_bounds__(kEdLanes) k_expdeg_tile(const float* __restrict__ w, const float* __restrict__ a,
+                                                          uint64_t n, float* __restrict__ part) {
+  constexpr int R = kEdRowsPerLane;
+  const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * kEdRows + threadIdx.x;
   const uint64_t j0 = static_cast<uint64_t>(blockIdx.y) * kEdCols;
   const uint64_t jn = (n - j0 < static_cast<uint64_t>(kEdCols)) ? (n - j0) : kEdCols;
-  const float ai = (i < n) ? a[i] : 0.0f;
-  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+  float ai[R], s[R][4];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t i = i0 + static_cast<uint64_t>(r) * kEdLanes;
+    ai[r] = (i < n) ? a[i] : 0.0f;
+    s[r][0] = s[r][1] = s[r][2] = s[r][3] = 0.0f;
+  }
   const float* __restrict__ wc = w + j0;
   uint64_t jj = 0;
-  for (; jj + 4 <= jn; jj += 4) {
-    s0 += fminf(ai * wc[jj + 0], 1.0f);
-    s1 += fminf(ai * wc[jj + 1], 1.0f);
-    s2 += fminf(ai * wc[jj + 2], 1.0f);
-    s3 += fminf(ai * wc[jj + 3], 1.0f);
+  for (; jj + kEdUnroll <= jn; jj += kEdUnroll) {
+    float wv[kEdUnroll];
+#pragma unroll
+    for (int q = 0; q < kEdUnroll; ++q) wv[q] = wc[jj + q];
+#pragma unroll
+    for (int q = 0; q < kEdUnroll; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[r][q & 3] += fminf(ai[r] * wv[q], 1.0f);
   }
-  for (; jj < jn; ++jj) s0 += fminf(ai * wc[jj], 1.0f);
-  if (i < n) part[static_cast<uint64_t>(blockIdx.y) * n + i] = (s0 + s1) + (s2 + s3);
+  // ragged tail of the last tile (kEdUnroll divides kEdCols)
+#pragma unroll
+  for (int q = 0; q < kEdUnroll; ++q)
+    if (jj + q < jn)
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[r][q & 3] += fminf(ai[r] * wc[jj + q], 1.0f);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t i = i0 + static_cast<uint64_t>(r) * kEdLanes;
+    if (i < n) part[static_cast<uint64_t>(blockIdx.y) * n + i] = (s[r][0] + s[r][1]) + (s[r][2] + s[r][3]);
+  }
 }
 
 // row sums of the tile partials in float64, minus the own term
@@ -63,35 +109,96 @@ __global__ void __launch_bounds__(256) k_expdeg_rows(const float* __restrict__ w
   d[i] = s;
 }
 
-// adjoint tile: partA = sum_{j in tile, x_ij < 1} w_j, partB = sum ... g_j w_j
-__global__ void __launch_bounds__(kEdRows) k_expdeg_bwd_tile(const float* __restrict__ w, const float* __restrict__ a,
-                                                             const float* __restrict__ gw, uint64_t n,
-                                                             float* __restrict__ partA, float* __restrict__ partB) {
-  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kEdRows + threadIdx.x;
+// Mask of the adjoint as one clamped multiply-add.  For a row with threshold
+// t = 1.x * 2^e (cap_threshold) and k = 2^(24 - e), the exact value (t - w) k
+// is >= 1 whenever w < t: either w >= t/2, where t and w are both multiples
+// of 2^(e - 24), or w < t/2 and the difference exceeds 2^(e - 1).  It is <= 0
+// when w >= t, and a fused multiply-add rounds it once, so clamping to [0, 1]
+// yields exactly 1.0 or 0.0.  k stays a normal float for e >= -100 and for
+// t = inf (then t k = inf and every finite w passes); a wave holding a row
+// with a smaller threshold takes the plain comparison instead.
+struct MaskRow {
+  float k, tk;
+};
+
+__device__ inline bool mask_row(float t, MaskRow* m) {
+  const int e = static_cast<int>((__float_as_uint(t) >> 23) & 0xFFu) - 127;
+  m->k = __uint_as_float(static_cast<uint32_t>(127 + 24 - e) << 23);
+  m->tk = t * m->k;
+  return e >= -100;
+}
+
+template <bool kFma>
+__device__ inline float mask_of(float wj, float t, const MaskRow& m) {
+  if constexpr (kFma) return __builtin_amdgcn_fmed3f(__builtin_fmaf(-wj, m.k, m.tk), 0.0f, 1.0f);
+  return wj < t ? 1.0f : 0.0f;
+}
+
+// adjoint tile: partA = sum_{j in tile, x_ij < 1} w_j, partB = sum ... g_j w_j.
+// The mask (0.0 or 1.0) is applied with a fused multiply-add: w * 1 and g * 0
+// are exact, so each step rounds as the plain masked sum does (for finite g).
+// Column j goes to accumulator j mod 2 of every row.
+template <bool kFma>
+__device__ inline void bwd_columns(const float* __restrict__ wc, const float* __restrict__ gc, uint64_t jn,
+                                   const float (&ti)[kEdRowsPerLane], const MaskRow (&mr)[kEdRowsPerLane],
+                                   float (&A)[kEdRowsPerLane][2], float (&B)[kEdRowsPerLane][2]) {
+  constexpr int R = kEdRowsPerLane;
+  uint64_t jj = 0;
+  for (; jj + kEdUnroll <= jn; jj += kEdUnroll) {
+    float wv[kEdUnroll], gv[kEdUnroll];
+#pragma unroll
+    for (int q = 0; q < kEdUnroll; ++q) {
+      wv[q] = wc[jj + q];
+      gv[q] = gc[jj + q];
+    }
+#pragma unroll
+    for (int q = 0; q < kEdUnroll; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float m = mask_of<kFma>(wv[q], ti[r], mr[r]);
+        A[r][q & 1] = __builtin_fmaf(wv[q], m, A[r][q & 1]);
+        B[r][q & 1] = __builtin_fmaf(gv[q], m, B[r][q & 1]);
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < kEdUnroll; ++q)
+    if (jj + q < jn)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float m = mask_of<kFma>(wc[jj + q], ti[r], mr[r]);
+        A[r][q & 1] = __builtin_fmaf(wc[jj + q], m, A[r][q & 1]);
+        B[r][q & 1] = __builtin_fmaf(gc[jj + q], m, B[r][q & 1]);
+      }
+}
+
+__global__ void __launch_bounds__(kEdLanes) k_expdeg_bwd_tile(const float* __restrict__ w, const float* __restrict__ thr,
+                                                              const float* __restrict__ gw, uint64_t n,
+                                                              float* __restrict__ partA, float* __restrict__ partB) {
+  constexpr int R = kEdRowsPerLane;
+  const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * kEdRows + threadIdx.x;
   const uint64_t j0 = static_cast<uint64_t>(blockIdx.y) * kEdCols;
   const uint64_t jn = (n - j0 < static_cast<uint64_t>(kEdCols)) ? (n - j0) : kEdCols;
-  const float ai = (i < n) ? a[i] : 0.0f;
-  float A0 = 0.0f, A1 = 0.0f, B0 = 0.0f, B1 = 0.0f;
-  const float* __restrict__ wc = w + j0;
-  const float* __restrict__ gc = gw + j0;
-  uint64_t jj = 0;
-  for (; jj + 2 <= jn; jj += 2) {
-    const float w0 = wc[jj], w1 = wc[jj + 1];
-    const bool m0 = ai * w0 < 1.0f, m1 = ai * w1 < 1.0f;
-    A0 += m0 ? w0 : 0.0f;
-    B0 += m0 ? gc[jj] : 0.0f;
-    A1 += m1 ? w1 : 0.0f;
-    B1 += m1 ? gc[jj + 1] : 0.0f;
+  float ti[R], A[R][2], B[R][2];
+  MaskRow mr[R];
+  bool fast = true;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t i = i0 + static_cast<uint64_t>(r) * kEdLanes;
+    ti[r] = (i < n) ? thr[i] : 1.0f;  // rows past n: any normal threshold, never stored
+    fast = mask_row(ti[r], &mr[r]) && fast;
+    A[r][0] = A[r][1] = B[r][0] = B[r][1] = 0.0f;
   }
-  for (; jj < jn; ++jj) {
-    const float w0 = wc[jj];
-    const bool m0 = ai * w0 < 1.0f;
-    A0 += m0 ? w0 : 0.0f;
-    B0 += m0 ? gc[jj] : 0.0f;
-  }
-  if (i < n) {
-    partA[static_cast<uint64_t>(blockIdx.y) * n + i] = A0 + A1;
-    partB[static_cast<uint64_t>(blockIdx.y) * n + i] = B0 + B1;
+  if (__builtin_amdgcn_ballot_w64(!fast) == 0)
+    bwd_columns<true>(w + j0, gw + j0, jn, ti, mr, A, B);
+  else
+    bwd_columns<false>(w + j0, gw + j0, jn, ti, mr, A, B);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t i = i0 + static_cast<uint64_t>(r) * kEdLanes;
+    if (i < n) {
+      partA[static_cast<uint64_t>(blockIdx.y) * n + i] = A[r][0] + A[r][1];
+      partB[static_cast<uint64_t>(blockIdx.y) * n + i] = B[r][0] + B[r][1];
+    }
   }
 }
 
@@ -124,10 +231,8 @@ __global__ void __launch_bounds__(256) k_expdeg_bwd_rows(const float* __restrict
     B[i] = sb;
     t = g[i] * static_cast<double>(a[i]) * sa;
   }
-  uint64_t tot;
   Dbl2 td;
   (void)block_exclusive<Dbl2>(Dbl2{t, 0.0}, &td);
-  (void)tot;
   if (threadIdx.x == 0) tpart[blockIdx.x] = td.a;
 }
 

@@ -63,6 +63,34 @@ def test_backward_matches_float64(cg, n, s_dep):
     assert err < 1e-4, err
 
 
+@pytest.mark.parametrize("case", ["tiny_thresholds", "zero_weights"])
+def test_backward_mask_edge_cases(cg, case):
+    """The adjoint forms its mask w_j < t_i with a clamped multiply-add that
+    is exact only for thresholds t_i >= 2^-100; a wave holding a smaller
+    one takes the plain comparison.  tiny_thresholds: S far below sum(w), so
+    rows with w_i ~ 1 have t_i ~ 1e-31 and share waves with rows of normal
+    thresholds; zero_weights: t_i = inf, every column passes."""
+    n = 1500
+    rng = np.random.default_rng(77)
+    if case == "tiny_thresholds":
+        big = rng.random(n) < 0.3
+        w = np.where(big, 1.0 + rng.random(n), 1e-33 * (1.0 + rng.random(n))).astype(np.float32)
+        S, s_dep = 1e-31, False
+    else:
+        w = _w32(n, 78)
+        w[rng.random(n) < 0.1] = 0.0
+        S, s_dep = float(np.sum(w.astype(np.float64))), True
+    w64 = w.astype(np.float64)
+    d = cg.cl_expected_degree(_dev32(w), S).cpu().numpy()
+    ref = O.expdeg_brute(w64, S)
+    assert np.max(np.abs(d - ref) / np.maximum(ref, 1.0)) < 1e-5
+    g = rng.standard_normal(n)
+    got = cg.cl_expected_degree_backward(_dev32(w), S, _dev64(g), s_dep).cpu().numpy().astype(np.float64)
+    gref = O.expdeg_grad_brute(w64, S, g, s_depends_on_w=s_dep)
+    err = np.linalg.norm(got - gref) / np.linalg.norm(gref)
+    assert err < 1e-4, err
+
+
 def test_full_size_forward_backward(cg):
     """n = 1e5 capped targets, 1e10 pairs: against the float64 closed forms."""
     t = W.config_calib()
