@@ -25,7 +25,8 @@ writing), offsets, compaction of the slots into the contiguous edge list.
   on n = 1e5 (1e10 pairs), against the VALU lane-operation peak;
 * partition_ablation: generation-kernel time with work units of equal
   expected cost (Eq. 5) vs units of equal source counts (Sec. 4's naive
-  consecutive partition), same number of units;
+  consecutive partition), same number of units; and the degree kernel under
+  those two and round-robin units (Sec. 4's RRP);
 * batched: 256 uneven graphs in one captured HIP graph vs 256 plain calls;
 * cpu_baseline: the CPU oracle on a bounded sample of the same workload.
 """
@@ -315,7 +316,9 @@ def bench_expdeg(cg, W, torch, dev, reps=5):
 def bench_partition(cg, torch, w, seed):
     """Sec. 4's comparison on one GPU: work units of equal expected cost
     (Eq. 5 applied to lanes) vs units of equal numbers of sources, same unit
-    count; generation-kernel time of each (same output)."""
+    count; generation-kernel time of each (same output).  Then the degree
+    kernel under those two and round-robin units (RRP over segments), timed
+    with events around cl_degrees (which includes one small header read)."""
     S = cg.cl_weight_sum(w)
     out = {}
     for name, pol in (("equal_cost_ms", 0), ("equal_sources_ms", 1)):
@@ -329,6 +332,28 @@ def bench_partition(cg, torch, w, seed):
         out["edges"] = plan.total
         del plan
     out["slowdown_equal_sources"] = out["equal_sources_ms"] / out["equal_cost_ms"]
+    # the degree kernel (same candidates, no edge output) under all three unit
+    # policies, round robin included (its units do not give ordered edge runs)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ref = None
+    out["degrees_identical"] = True
+    for name, pol in (("equal_cost", 0), ("equal_sources", 1), ("round_robin", 2)):
+        plan = cg.cl_plan([cg.Task(w, S, seed)], tuning={"partition": pol})
+        deg = torch.zeros(w.numel() + 1, dtype=torch.int32, device=w.device)
+        ms = []
+        for _ in range(3):
+            deg.zero_()
+            e0.record()
+            cg.cl_degrees(plan, deg=deg)
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        out[f"degrees_{name}_ms"] = min(ms)
+        if ref is None:
+            ref = deg
+        else:
+            out["degrees_identical"] = out["degrees_identical"] and bool(torch.equal(deg, ref))
+        del plan
     return out
 
 

@@ -74,7 +74,12 @@ typedef struct cl_tuning {
                               of the overflow replay: about half of the lanes overflow) */
   uint32_t partition;      /* work units: 0 = equal expected cost (Eq. 5 applied to lanes, default);
                               1 = equal numbers of sources (the naive consecutive partition Sec. 4
-                              compares against; heavy sources then serialise their unit) */
+                              compares against; heavy sources then serialise their unit);
+                              2 = round robin (Sec. 4's RRP applied to segments: unit i of L takes
+                              segments i, i + L, i + 2L, ...).  A round-robin unit's edges are not
+                              contiguous in (u, v) order, so 2 is accepted by cl_plan only (then
+                              cl_degrees); cl_count and cl_sample return CL_ERR_INVALID_ARG.
+                              Other values: CL_ERR_INVALID_ARG. */
 } cl_tuning;
 
 /* ---------------------------------------------------------------------------

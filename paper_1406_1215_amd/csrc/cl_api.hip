@@ -421,6 +421,9 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
   cl_status st = check_graphs(g, G);
   if (st != CL_OK) return st;
   if (!m_out) return CL_ERR_INVALID_ARG;
+  const uint32_t policy = t ? t->partition : 0u;
+  // round-robin units do not produce (u, v)-ordered runs: plan only
+  if (policy > 2 || (policy == 2 && mode != 2)) return CL_ERR_INVALID_ARG;
   const FixedLayout F = fixed_layout(g, G);
   if (ws_required) *ws_required = F.bytes;
   if (!ws || ws_bytes < F.bytes) return CL_ERR_WORKSPACE;
@@ -442,7 +445,7 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
     d.q_off = qo;
     d.r_off = ro;
     d.budget = bu;
-    d.policy = (t && t->partition == 1) ? 1u : 0u;
+    d.policy = policy;
     qo += g[i].n + 1;
     ro += (g[i].u_end - g[i].u_begin) + 1;
     desc[i] = d;

@@ -372,6 +372,8 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
       // segment and unit indices are 32-bit: a graph above 2^32 - 1 segments
       // is refused (n < 2^32 sources leaves room for ~1e9 heavy segments)
       if (nseg > 0xFFFFFFFFull) atomicOr(&d.status, kStCapacity);
+      // round-robin units step by L <= nseg: keep sg + L below 2^32
+      if (d.policy == 2 && nseg > 0x80000000ull) atomicOr(&d.status, kStCapacity);
       d.L = L;
       d.NH = nh;
       cost = (L > 0) ? Z : 0;
@@ -505,7 +507,7 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
     const uint64_t r = i - d.r_off;
     if (r >= d.nr) continue;
     A[i] = d.w[d.u_begin + r] / d.S;  // a_u of Alg. 1, once per source
-    if (d.L == 0) continue;
+    if (d.L == 0 || d.policy == 2) continue;   // round-robin starts are set with the groups
     const uint64_t L = d.L;
     const uint64_t Z = d.Z;
     const uint64_t cex = C[i] - d.C0;
@@ -543,7 +545,8 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
   }
 }
 
-// group -> graph map, and the padding lanes (empty: start = (u_end, 0))
+// group -> graph map, the padding lanes (empty: start = (u_end, 0)) and the
+// starts of round-robin units
 __global__ void __launch_bounds__(256) k_lane_groups(const WsHeader* hdr) {
   if (hdr->status) return;
   const GraphDesc* desc = hdr->desc;
@@ -556,7 +559,9 @@ __global__ void __launch_bounds__(256) k_lane_groups(const WsHeader* hdr) {
     const GraphDesc& d = desc[g];
     hdr->group_graph[q] = g;
     for (uint64_t li = (l0 - d.lane_off); li < (l0 - d.lane_off) + kLaneGroup; ++li) {
-      if (li >= d.L) {
+      if (li < d.L && d.policy == 2) {
+        hdr->lane_seg[d.lane_off + li] = static_cast<uint32_t>(li);   // round robin: first segment i
+      } else if (li >= d.L) {
         hdr->lane_seg[d.lane_off + li] = static_cast<uint32_t>(d.SB1 - d.SB0);
         if (hdr->lane_cum) hdr->lane_cum[d.lane_off + li] = d.C1 - d.C0;
       }
@@ -612,11 +617,13 @@ struct LaneCtx {
   uint32_t n;
   uint32_t u_begin, u_heavy_end;  // sources [u_begin, u_heavy_end) are heavy
   uint32_t NH;                    // heavy segments; segment index NH + i is light source u_heavy_end + i
+  uint32_t stride;                // segment step inside a unit: 1, or L for round-robin units
   gptr<u32x4> hseg;               // graph's heavy segments (u, k, j, send)
 };
 
 // State of one lane inside its current work unit: the unit is the run of
-// segments [sg, sg_end) of the lane plan (graph-relative segment indices);
+// segments [sg, sg_end) of the lane plan (graph-relative segment indices),
+// taken with step cx.stride (1; L for round-robin units);
 // (u, k) is the open segment, j its next candidate, send its end, t the index
 // of its next draw.
 struct LaneRun {
@@ -648,7 +655,7 @@ __device__ __forceinline__ void open_segment(LaneRun& s, const LaneCtx& cx) {
   s.p = any ? cap1(s.a * wj) : 0.0;
   s.inseg = (s.p > 0.0);
   s.t = 0;
-  ++s.sg;
+  s.sg += cx.stride;
 }
 
 // ln(1 - p) of ln_one_minus without the branch: both forms share one division
@@ -867,6 +874,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
   RoundKeys rk{};
   uint64_t unit_end = 0;     // one past the graph's last (padded) unit
   uint32_t nseg = 0;         // segments of the graph
+  bool rr = false;           // round-robin units
   uint32_t* degp = nullptr;  // degree mode: the graph's degree array
   uint32_t cnext = 0, cend = 0, cgraph = kNone;
   bool queue_done = false;
@@ -922,6 +930,8 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
           cx.u_begin = uni32(static_cast<uint32_t>(d.u_begin));
           cx.u_heavy_end = cx.u_begin + uni32(static_cast<uint32_t>(d.H));
           cx.NH = uni32(static_cast<uint32_t>(d.NH));
+          rr = (uni32(d.policy) == 2);
+          cx.stride = rr ? uni32(static_cast<uint32_t>(d.L)) : 1u;
           cx.A = to_global(uniptr(hdr->A) + uni64(d.r_off));
           cx.hseg = to_global(reinterpret_cast<const u32x4*>(uniptr(hdr->hseg) + uni64(d.hs_off)));
           rk = philox_round_keys(uni64(d.seed));
@@ -936,7 +946,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
         if (idle && mine < cend) {
           unit = mine;
           s.sg = lane_seg[unit];
-          s.sg_end = (unit + 1 < unit_end) ? lane_seg[unit + 1] : nseg;
+          s.sg_end = (rr || unit + 1 >= unit_end) ? nseg : lane_seg[unit + 1];
           s.inseg = false;
           if constexpr (kMode == 0) {
             em = Emit{0u};

@@ -43,7 +43,8 @@ struct GraphDesc {
   uint64_t m;        // edges
   uint64_t edge_off; // first edge in the batch output
   uint32_t status;
-  uint32_t policy;   // host: 0 = units of equal cost, 1 = units of equal source counts
+  uint32_t policy;   // host: 0 = units of equal cost, 1 = units of equal source counts,
+                     // 2 = round robin (unit i takes segments i, i + L, i + 2L, ...)
 };
 
 struct Triple {

@@ -109,3 +109,45 @@ def test_parts_give_the_whole_graph(cg):
     res = parts.degrees(_dev(w), S, 5, parts=5)
     assert res["edges"] == m
     assert np.array_equal(res["deg"].cpu().numpy().view(np.uint32).astype(np.int64), want)
+
+
+@pytest.mark.parametrize("budget", [32, 192])
+@pytest.mark.parametrize("policy", [1, 2])
+def test_degrees_under_every_unit_policy(cg, policy, budget):
+    """Units of equal source counts (1) and round-robin units (2, Sec. 4's
+    RRP over segments: unit i takes segments i, i + L, ...) change only the
+    schedule: the degrees equal the oracle's, bit for bit, on a workload
+    with heavy (segmented) sources."""
+    w = W.config_plain(n=200_000)
+    S = O.exact_sum(w)
+    want, _ = _oracle_degrees(w, S, 9)
+    plan = cg.cl_plan([cg.Task(_dev(w), S, 9)], tuning={"partition": policy, "lane_budget": budget})
+    assert cg.cl_plan_info(plan)["heavy_segments"] > 0
+    (deg,) = cg.cl_degrees(plan)
+    assert np.array_equal(deg.cpu().numpy().view(np.uint32).astype(np.int64), want)
+
+
+def test_round_robin_batch_and_ranges(cg):
+    """Round-robin units over a batch of uneven graphs and a source range."""
+    rng = np.random.default_rng(31)
+    ws = [W.powerlaw_capped(int(n), a, 2.0, np.random.default_rng(int(n)))
+          for n, a in zip(rng.integers(1, 20000, 5), rng.uniform(2.0, 3.0, 5))]
+    tasks, wants = [], []
+    for i, w in enumerate(ws):
+        S = O.exact_sum(w)
+        u0, u1 = (w.size // 3, w.size) if i == 0 else (0, w.size)
+        wants.append(_oracle_degrees(w, S, 200 + i, u0, u1)[0])
+        tasks.append(cg.Task(_dev(w), S, 200 + i, u0, u1))
+    plan = cg.cl_plan(tasks, tuning={"partition": 2})
+    for d, want in zip(cg.cl_degrees(plan), wants):
+        assert np.array_equal(d.cpu().numpy().view(np.uint32).astype(np.int64), want)
+
+
+@pytest.mark.parametrize("planner", ["cl_count", "cl_sample"])
+def test_round_robin_refused_where_edges_are_written(cg, planner):
+    w = W.config_small()
+    S = O.exact_sum(w)
+    with pytest.raises(cg.ClError):
+        getattr(cg, planner)([cg.Task(_dev(w), S, 1)], tuning={"partition": 2})
+    with pytest.raises(cg.ClError):
+        cg.cl_plan([cg.Task(_dev(w), S, 1)], tuning={"partition": 3})
