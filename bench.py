@@ -23,6 +23,8 @@ writing), offsets, compaction of the slots into the contiguous edge list.
 * two_pass: the count-then-replay path (count pass, offsets, write pass);
 * expected_degree: the float32 tiled expected-degree kernel and its adjoint
   on n = 1e5 (1e10 pairs), against the VALU lane-operation peak;
+* calibration: 200 Adam steps on log w against n = 1e5 capped targets, then
+  generation from the calibrated weights;
 * partition_ablation: generation-kernel time with work units of equal
   expected cost (Eq. 5) vs units of equal source counts (Sec. 4's naive
   consecutive partition), same number of units; and the degree kernel under
@@ -86,6 +88,7 @@ def parse():
     ap.add_argument("--no-two-pass", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-expdeg", action="store_true")
+    ap.add_argument("--no-calib", action="store_true")
     ap.add_argument("--full-graph-degrees", action="store_true",
                     help="instead of the step: the degree sequence of the whole n=1e9 graph (exponent 2.1, mean "
                          "degree 500), every edge generated and consumed on the fly, part by part")
@@ -230,6 +233,8 @@ def main():
 
     if not args.no_expdeg:
         result["expected_degree"] = bench_expdeg(cg, W, torch, dev)
+    if not args.no_calib:
+        result["calibration"] = bench_calibration(cg, W, torch, dev)
 
     if not args.no_batched:
         result["batched"] = bench_batched(args, cg, W, torch, np, dev)
@@ -311,6 +316,28 @@ def bench_expdeg(cg, W, torch, dev, reps=5):
         out[f"{name}_pairs_per_s"] = n * n / (ms * 1e-3)
         out[f"{name}_alu_frac"] = n * n * ops / (ms * 1e-3) / PEAK_LANE_OPS
     return out
+
+
+def bench_calibration(cg, W, torch, dev, steps=200):
+    """The calibration loop on n = 1e5 capped targets: Adam on log w for 200
+    steps (forward + adjoint kernels each step, plus torch's elementwise
+    work and one scalar read for S), then generation from the sorted
+    calibrated weights; wall time of each."""
+    from paper_1406_1215_amd.calibrate import calibrate
+    t = torch.from_numpy(W.config_calib()).to(dev)
+    calibrate(t, steps=3)                          # warm-up
+    res = calibrate(t, steps=steps, lr=0.05)
+    S = cg.cl_weight_sum(res.w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = cg.cl_sample([cg.Task(res.w, S, 11)])
+    edges = cg.cl_generate(plan)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    del edges
+    return {"n": int(t.numel()), "adam_steps": steps, "seconds": res.seconds,
+            "ms_per_step": res.seconds / steps * 1e3, "max_rel_err": res.max_rel_err,
+            "generation_edges": int(plan.total), "generation_ms": gen_s * 1e3}
 
 
 def bench_partition(cg, torch, w, seed):

@@ -279,7 +279,8 @@ cl_status cl_weight_sum(const double* w, uint64_t n, void* ws, uint64_t ws_bytes
   h.q_off = 0;
   CL_TRY(hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_zero_u64, dim3(16), dim3(256), 0, s, bins, static_cast<uint64_t>(2 * kBins));
-  const uint32_t cap = stream_grid_cap();
+  // few blocks: every block adds its nonzero bins to the same few global words
+  const uint32_t cap = std::max<uint32_t>(cus_of_current_device(), 1) * 4;
   hipLaunchKernelGGL((k_validate<true>), dim3(grid_for(n + 1, 256, cap)), dim3(256), 0, s, d, 1u, n + 1, bins);
   hipLaunchKernelGGL(k_sum_finalize, dim3(1), dim3(64), 0, s, bins, S_dev, &d->status);
   CL_TRY(hipGetLastError());

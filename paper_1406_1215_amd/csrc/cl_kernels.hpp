@@ -66,7 +66,18 @@ __device__ __forceinline__ void bin_flush(unsigned long long* lds, int b, uint64
 
 // Validates every weight of every graph (slot space of the Q prefix: n + 1
 // slots per graph, the last one of each graph ignored).  With bins != null
-// (single graph), also accumulates the exact sum.
+// (single graph), also accumulates the exact sum.  A single graph's fields
+// are read once and its flags ORed once per thread; each thread handles
+// kValUnroll slots per step, their loads issued together.
+constexpr int kValUnroll = 4;
+
+struct ValView {
+  const double* w;
+  uint64_t q_off, n;
+  double S;
+  uint32_t g;
+};
+
 template <bool want_sum>
 __global__ void __launch_bounds__(256) k_validate(GraphDesc* desc, uint32_t G, uint64_t total_slots,
                                                   unsigned long long* bins) {
@@ -75,46 +86,66 @@ __global__ void __launch_bounds__(256) k_validate(GraphDesc* desc, uint32_t G, u
     for (int i = threadIdx.x; i < 2 * kBins; i += blockDim.x) lbins[i] = 0ull;
     __syncthreads();
   }
+  auto view = [&](uint32_t g) {
+    const GraphDesc& d = desc[g];
+    return ValView{d.w, d.q_off, d.n, d.S, g};
+  };
+  const ValView v0 = view(0);
+  uint32_t flags0 = 0;     // single graph: its flags, ORed at the end
   int cur_b = -1;
   uint64_t acc_lo = 0, acc_hi = 0;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total_slots; i += stride) {
-    const uint32_t g = find_graph(G, i, [&](uint32_t x) { return desc[x].q_off; });
-    const GraphDesc& d = desc[g];
-    const uint64_t v = i - d.q_off;
-    if (v >= d.n) continue;
-    const double x = d.w[v];
-    const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(x));
-    const uint32_t ex = static_cast<uint32_t>((bits >> 52) & 0x7FF);
-    uint32_t flag = 0;
-    if (ex == 0x7FF) {
-      flag |= kStNonfinite;
-    } else if (x < 0.0) {
-      flag |= kStNegative;
-    } else {
-      if (v + 1 < d.n) {
-        const double y = d.w[v + 1];
-        if (x < y) flag |= kStUnsorted;
-      }
-      if (v == 0) {
-        if (x > d.S || (x > 0.0 && x < 0x1.0p-960)) flag |= kStBadS;
-      }
-      if (want_sum) {
-        const int b = (ex == 0) ? 1 : static_cast<int>(ex);
-        uint64_t mant = bits & 0x000FFFFFFFFFFFFFull;
-        if (ex != 0) mant |= 0x0010000000000000ull;
-        if (b != cur_b) {
-          bin_flush(lbins, cur_b, acc_lo, acc_hi);
-          cur_b = b;
-          acc_lo = 0;
-          acc_hi = 0;
+  for (uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i0 < total_slots;
+       i0 += kValUnroll * stride) {
+    double x[kValUnroll], y[kValUnroll];
+    ValView dv[kValUnroll];
+    bool live[kValUnroll];
+#pragma unroll
+    for (int r = 0; r < kValUnroll; ++r) {
+      const uint64_t i = i0 + r * stride;
+      dv[r] = (G == 1) ? v0 : view(find_graph(G, i < total_slots ? i : 0, [&](uint32_t q) { return desc[q].q_off; }));
+      const uint64_t v = i - dv[r].q_off;
+      live[r] = (i < total_slots) && (v < dv[r].n);
+      x[r] = live[r] ? dv[r].w[v] : 0.0;
+      y[r] = (live[r] && v + 1 < dv[r].n) ? dv[r].w[v + 1] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < kValUnroll; ++r) {
+      if (!live[r]) continue;
+      const uint64_t v = i0 + r * stride - dv[r].q_off;
+      const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(x[r]));
+      const uint32_t ex = static_cast<uint32_t>((bits >> 52) & 0x7FF);
+      uint32_t flag = 0;
+      if (ex == 0x7FF) {
+        flag |= kStNonfinite;
+      } else if (x[r] < 0.0) {
+        flag |= kStNegative;
+      } else {
+        if (x[r] < y[r]) flag |= kStUnsorted;   // y = 0 past the last weight
+        if (v == 0) {
+          if (x[r] > dv[r].S || (x[r] > 0.0 && x[r] < 0x1.0p-960)) flag |= kStBadS;
         }
-        acc_lo += mant & 0xFFFFFFFFull;
-        acc_hi += mant >> 32;
+        if (want_sum) {
+          const int b = (ex == 0) ? 1 : static_cast<int>(ex);
+          uint64_t mant = bits & 0x000FFFFFFFFFFFFFull;
+          if (ex != 0) mant |= 0x0010000000000000ull;
+          if (b != cur_b) {
+            bin_flush(lbins, cur_b, acc_lo, acc_hi);
+            cur_b = b;
+            acc_lo = 0;
+            acc_hi = 0;
+          }
+          acc_lo += mant & 0xFFFFFFFFull;
+          acc_hi += mant >> 32;
+        }
+      }
+      if (flag) {
+        if (G == 1) flags0 |= flag;
+        else atomicOr(&desc[dv[r].g].status, flag);
       }
     }
-    if (flag) atomicOr(&desc[g].status, flag);
   }
+  if (flags0) atomicOr(&desc[0].status, flags0);
   if (want_sum) {
     bin_flush(lbins, cur_b, acc_lo, acc_hi);
     __syncthreads();
@@ -511,22 +542,23 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
     const uint64_t L = d.L;
     const uint64_t Z = d.Z;
     const uint64_t cex = C[i] - d.C0;
-    const uint64_t cin = C[i + 1] - d.C0;
-    const uint64_t sbi = SB[i];
-    const uint64_t K = SB[i + 1] - sbi;
     if (d.policy == 1) {
       // equal source counts: unit li starts at source floor(li nr / L), segment 0
       // (L <= nr, so a source starts at most one unit)
       const uint64_t li = (r * L + d.nr - 1) / d.nr;          // ceil(r L / nr)
       if (li < L && (li * d.nr) / L == r) {
-        lane_seg[d.lane_off + li] = static_cast<uint32_t>(sbi - d.SB0);
+        lane_seg[d.lane_off + li] = static_cast<uint32_t>(SB[i] - d.SB0);
         if (lane_cum) lane_cum[d.lane_off + li] = cex;
       }
       continue;
     }
+    const uint64_t cin = C[i + 1] - d.C0;
     uint64_t ilo = (r == 0) ? 0 : lane_floor(cex, L, Z) + 1;
     uint64_t ihi = lane_floor(cin, L, Z);
     if (ihi > L - 1) ihi = L - 1;
+    if (ilo > ihi) continue;   // no unit starts at this source (most sources)
+    const uint64_t sbi = SB[i];
+    const uint64_t K = SB[i + 1] - sbi;
     const double cnode = static_cast<double>(cin - cex);
     for (uint64_t li = ilo; li <= ihi; ++li) {
       const double Ti = static_cast<double>(li) * static_cast<double>(Z) / static_cast<double>(L);
