@@ -61,3 +61,10 @@ def test_host_side_argument_checks():
     assert req.value == fixed.value
     bounds = (ctypes.c_uint64 * 3)()
     assert L.cl_partition(None, 0, 1.0, 0, None, 0, bounds, None, None) == -1
+    # round-robin units are for plans without edge output; unknown policies refused
+    rr = ctypes.pointer(clgen.cl_tuning(0, 0, 0, 2))
+    assert L.cl_count(g, 1, rr, None, 0, m, ctypes.byref(req), None) == -1
+    assert L.cl_sample(g, 1, rr, None, 0, m, ctypes.byref(req), None) == -1
+    bad = ctypes.pointer(clgen.cl_tuning(0, 0, 0, 3))
+    assert L.cl_plan(g, 1, bad, None, 0, ctypes.byref(req), None) == -1
+    assert L.cl_plan(g, 1, rr, None, 0, ctypes.byref(req), None) == -6   # accepted; workspace too small
