@@ -11,15 +11,16 @@ writing), offsets, compaction of the slots into the contiguous edge list.
 * roofline: the one-pass generation kernel (Alg. 1 per lane, edges staged
   into 64-byte chunks of per-lane slots), timed with HIP events on its stream.
   Its bound is the memory system: every visited candidate reads one weight
-  w_v at an essentially random position (8 algorithmic bytes, one 64-byte
+  w_v at an essentially random position (8 algorithmic bytes, one 128-byte
   line from HBM or the Infinity Cache on an L2 miss) and every kept edge
-  writes 8 bytes.  achieved = (8 B x candidates + 8 B x edges) / launch time
+  writes a 4-byte slot word (v; a mark and u are added where the source
+  changes).  achieved = (8 B x candidates + 4 B x slot words) / launch time
   against 8 TB/s; traffic = the kernel's measured HBM bytes (FETCH_SIZE +
   WRITE_SIZE, scaled by a copy kernel of known size) from the committed
   counter summary when it was taken on the current kernel source;
   alu_view gives the same launch against the VALU peak;
-* hbm_write: bytes of edges written per second by that kernel and by the
-  compaction copy, against 8 TB/s;
+* hbm_write: bytes written per second by that kernel (slot words) and moved
+  by the compaction (slot words read, 8-byte edges written), against 8 TB/s;
 * two_pass: the count-then-replay path (count pass, offsets, write pass);
 * expected_degree: the float32 tiled expected-degree kernel and its adjoint
   on n = 1e5 (1e10 pairs), against the VALU lane-operation peak;
@@ -50,7 +51,8 @@ OPS_PER_CANDIDATE = 145          # operation count of one candidate step of the 
 # Without packed fp32 math an FMA issues at half this rate.
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
 BYTES_PER_CANDIDATE = 8           # w_v gathered
-BYTES_PER_EDGE = 8                # (u, v) uint32 pair written
+BYTES_PER_SLOT_WORD = 4           # slot words written: v per edge, (mark, u) per change of source
+BYTES_PER_EDGE = 8                # (u, v) uint32 pair of the edge list
 HBM_PEAK = 8.0e12                 # bytes/s
 METRIC = "edges/sec generated on 1 MI355X + % HBM write roofline; batched vs plain"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_generation_plain_1e7.json")
@@ -156,27 +158,32 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} steps")
-    copy_ms, lane_ms = [], []
     total_edges = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         total_edges += step()
-        ev1.synchronize()
-        copy_ms.append(ev0.elapsed_time(ev1))
-        lane_ms.append(cg.cl_plan_info(plan)["lane_kernel_ms"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
+    # kernel times of the same step, outside the timed region (reading them
+    # back costs a host round trip per step)
+    copy_ms, lane_ms = [], []
+    for _ in range(max(3, min(args.steps, 10))):
+        step()
+        ev1.synchronize()
+        copy_ms.append(ev0.elapsed_time(ev1))
+        lane_ms.append(cg.cl_plan_info(plan)["lane_kernel_ms"])
     m = plan.total
     info = cg.cl_plan_info(plan)
     cand = info["candidates"]
+    words = info["slot_words"]
     t_gen = sum(lane_ms) / len(lane_ms) / 1e3
     t_copy = sum(copy_ms) / len(copy_ms) / 1e3
     ms_step = elapsed / args.steps * 1e3
     value = total_edges / elapsed
     achieved_ops = cand * OPS_PER_CANDIDATE / t_gen
-    alg_bytes = BYTES_PER_CANDIDATE * cand + BYTES_PER_EDGE * m
+    alg_bytes = BYTES_PER_CANDIDATE * cand + BYTES_PER_SLOT_WORD * words
     achieved_bw = alg_bytes / t_gen
     traffic = traffic_per_launch()
     result = {
@@ -205,8 +212,10 @@ def main():
             "frac": achieved_bw / HBM_PEAK,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": int(alg_bytes),
-            "per_unit": "8 B per visited candidate (w_v gather) + 8 B per edge written",
+            "per_unit": "8 B per visited candidate (w_v gather) + 4 B per slot word written "
+                        "(v of each edge; a mark and u where the source changes)",
             "candidates_per_launch": int(cand),
+            "slot_words_per_launch": int(words),
             "launch_ms": t_gen * 1e3,
         },
         "alu_view": {
@@ -217,10 +226,10 @@ def main():
             "ops_per_candidate": OPS_PER_CANDIDATE,
         },
         "hbm_write": {
-            "generation_GBps": 8.0 * m / t_gen / 1e9,
-            "generation_frac_of_8TBps": 8.0 * m / t_gen / HBM_PEAK,
+            "generation_GBps": 4.0 * words / t_gen / 1e9,
+            "generation_frac_of_8TBps": 4.0 * words / t_gen / HBM_PEAK,
             "compaction_ms": t_copy * 1e3,
-            "compaction_GBps_read_plus_write": 16.0 * m / t_copy / 1e9,
+            "compaction_GBps_read_plus_write": (4.0 * words + 8.0 * m) / t_copy / 1e9,
             "whole_step_GBps": 8.0 * total_edges / elapsed / 1e9,
             "whole_step_frac_of_8TBps": 8.0 * total_edges / elapsed / HBM_PEAK,
         },

@@ -192,9 +192,12 @@ cl_status cl_degrees(void* ws, const cl_tuning* t, uint32_t* deg, uint64_t deg_l
  * candidates the lane kernel visited (the "edges + sources" work of Eq. 2-4,
  * rejections included); lane_kernel_ms is the duration of that kernel
  * (count pass or one pass), timed by HIP events on the caller's stream;
- * overflow_lanes counts one-pass lanes that exceeded their slot. */
+ * overflow_lanes counts one-pass lanes that exceeded their slot; slot_words
+ * is the number of 32-bit words the one pass needed for its slots (one per
+ * edge plus two per change of source inside a lane; 0 for other plans). */
 cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments, uint64_t* edges,
-                       uint64_t* candidates, float* lane_kernel_ms, uint32_t* overflow_lanes, void* stream);
+                       uint64_t* candidates, float* lane_kernel_ms, uint32_t* overflow_lanes,
+                       uint64_t* slot_words, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Digest of an edge list: acc += sum_i mix(mix(index_base + i) ^ (u_i 2^32 + v_i))

@@ -74,7 +74,7 @@ def lib():
                          _U64P, _P]),
         "cl_generate": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _U64, _P, _P]),
         "cl_plan_info": (S, [_P, _U64P, _U64P, _U64P, _U64P, ctypes.POINTER(ctypes.c_float),
-                              ctypes.POINTER(ctypes.c_uint32), _P]),
+                              ctypes.POINTER(ctypes.c_uint32), _U64P, _P]),
         "cl_hash_edges": (S, [_P, _U64, _U64, _P, _P]),
         "cl_degrees": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _P]),
         "cl_plan": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _U64, _U64P,
@@ -296,13 +296,14 @@ def cl_degrees(plan: Plan, deg: Optional[torch.Tensor] = None, stream=None) -> L
 def cl_plan_info(plan_or_ws, stream=None) -> dict:
     L = lib()
     ws = plan_or_ws.ws if isinstance(plan_or_ws, Plan) else plan_or_ws
-    lanes, nh, m, nc = _U64(0), _U64(0), _U64(0), _U64(0)
+    lanes, nh, m, nc, sw = _U64(0), _U64(0), _U64(0), _U64(0), _U64(0)
     ms = ctypes.c_float(0.0)
     ov = ctypes.c_uint32(0)
     code = L.cl_plan_info(_ptr(ws), ctypes.byref(lanes), ctypes.byref(nh), ctypes.byref(m), ctypes.byref(nc),
-                          ctypes.byref(ms), ctypes.byref(ov), _stream(stream))
+                          ctypes.byref(ms), ctypes.byref(ov), ctypes.byref(sw), _stream(stream))
     return {"status": code, "lanes": int(lanes.value), "heavy_segments": int(nh.value), "edges": int(m.value),
-            "candidates": int(nc.value), "lane_kernel_ms": float(ms.value), "overflow_lanes": int(ov.value)}
+            "candidates": int(nc.value), "lane_kernel_ms": float(ms.value), "overflow_lanes": int(ov.value),
+            "slot_words": int(sw.value)}
 
 
 def cl_hash_edges(edges: torch.Tensor, index_base: int = 0, acc: Optional[torch.Tensor] = None,

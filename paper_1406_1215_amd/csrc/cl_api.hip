@@ -109,10 +109,10 @@ FixedLayout fixed_layout(const cl_graph* g, uint32_t G) {
 
 struct VarLayout {
   uint64_t off_hseg, off_lstart, off_lcnt, off_lpos, off_lscan, off_groups, bytes;
-  uint64_t off_lcum, off_soff, off_sscan, off_slots, slot_cap;
+  uint64_t off_lcum, off_soff, off_sscan, off_lwords, off_slots, slot_cap;
 };
 
-// nh heavy segments, nl lanes; with one_pass, slot_cap edges of slots
+// nh heavy segments, nl lanes; with one_pass, slot_cap words of slots
 VarLayout var_layout(uint64_t base, uint64_t nh, uint64_t nl, bool one_pass, uint64_t slot_cap) {
   VarLayout V{};
   uint64_t off = align_up(base);
@@ -135,19 +135,23 @@ VarLayout var_layout(uint64_t base, uint64_t nh, uint64_t nl, bool one_pass, uin
     off = align_up(off + 8 * (nl + 1));
     V.off_sscan = off;
     off = align_up(off + 8 * (scan_tiles(nl + 1) + 8));
+    V.off_lwords = off;
+    off = align_up(off + 4 * std::max<uint64_t>(nl, 1));
     V.off_slots = off;
     V.slot_cap = slot_cap;
-    off = align_up(off + 8 * std::max<uint64_t>(slot_cap, 1));
+    off = align_up(off + 4 * std::max<uint64_t>(slot_cap, 1));
   }
   V.bytes = off;
   return V;
 }
 
-// upper bound of the slot capacities: sum (mu + 8 sqrt(mu) + 32) over the
-// lanes, with sum sqrt(mu) <= sqrt(lanes * sum mu)
-uint64_t slot_bound(uint64_t total_cost, uint64_t nl) {
+// upper bound of the slot capacities in words: sum (mu + 8 sqrt(mu) + 25 +
+// 2 segments + 15 of rounding) over the lanes, with sum sqrt(mu) <=
+// sqrt(lanes * sum mu)
+uint64_t slot_bound(uint64_t total_cost, uint64_t nl, uint64_t nseg) {
   const double mu = static_cast<double>(total_cost) / kCostUnit;
-  const double b = mu + 8.0 * std::sqrt(static_cast<double>(nl) * mu) + 40.0 * static_cast<double>(nl) + 64.0;
+  const double b = mu + 8.0 * std::sqrt(static_cast<double>(nl) * mu) + 40.0 * static_cast<double>(nl) +
+                   2.0 * static_cast<double>(nseg) + 64.0;
   return static_cast<uint64_t>(std::ceil(b));
 }
 
@@ -402,16 +406,17 @@ cl_status cl_workspace_size(const cl_graph* g, uint32_t G, const cl_tuning* t, u
   // estimate (when S = sum w): expected edges <= S/2, plan cost ~ 16 (S/2 + 2 range),
   // heavy segments ~ S/256
   const uint64_t bu = budget_units(t) / kCostUnit;
-  double nl = 0.0, nh = 0.0, cost = 0.0;
+  double nl = 0.0, nh = 0.0, cost = 0.0, nseg = 0.0;
   for (uint32_t i = 0; i < G; ++i) {
     const double nr = static_cast<double>(g[i].u_end - g[i].u_begin);
     nl += (g[i].S * 0.5 + 2.0 * nr) / static_cast<double>(bu) + kLaneGroup;
     nh += g[i].S / 256.0 + 64.0;
+    nseg += g[i].S / 256.0 + 64.0 + nr;
     cost += kCostUnit * (g[i].S * 0.5 + 2.0 * nr);
   }
   const uint64_t nl64 = static_cast<uint64_t>(nl) / kLaneGroup * kLaneGroup + kLaneGroup * G;
   const VarLayout V = var_layout(F.bytes, static_cast<uint64_t>(nh), nl64, one_pass != 0,
-                                 one_pass ? slot_bound(static_cast<uint64_t>(cost), nl64) : 0);
+                                 one_pass ? slot_bound(static_cast<uint64_t>(cost), nl64, static_cast<uint64_t>(nseg)) : 0);
   if (fixed_bytes) *fixed_bytes = F.bytes;
   if (estimate_bytes) *estimate_bytes = V.bytes;
   return CL_OK;
@@ -477,7 +482,7 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
 
   const bool one_pass = (mode == 1);
   const VarLayout V = var_layout(F.bytes, back.total_nh, back.total_nl, one_pass,
-                                 one_pass ? slot_bound(back.total_cost, back.total_nl) : 0);
+                                 one_pass ? slot_bound(back.total_cost, back.total_nl, back.total_seg) : 0);
   if (ws_required) *ws_required = V.bytes;
   if (ws_bytes < V.bytes) return CL_ERR_WORKSPACE;
   h.cap_nh = back.total_nh;
@@ -498,9 +503,11 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
     h.lane_cum = reinterpret_cast<uint64_t*>(base + V.off_lcum);
     h.slot_off = reinterpret_cast<uint64_t*>(base + V.off_soff);
     h.slot_scan_tmp = reinterpret_cast<uint64_t*>(base + V.off_sscan);
-    h.slots = reinterpret_cast<uint2*>(base + V.off_slots);
+    h.lane_words = reinterpret_cast<uint32_t*>(base + V.off_lwords);
+    h.slots = reinterpret_cast<uint32_t*>(base + V.off_slots);
     h.slot_cap = V.slot_cap;
   } else {
+    h.lane_words = nullptr;
     h.lane_cum = nullptr;
     h.slot_off = nullptr;
     h.slot_scan_tmp = nullptr;
@@ -587,7 +594,8 @@ cl_status cl_degrees(void* ws, const cl_tuning* t, uint32_t* deg, uint64_t deg_l
 }
 
 cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments, uint64_t* edges,
-                       uint64_t* candidates, float* lane_kernel_ms, uint32_t* overflow_lanes, void* stream) {
+                       uint64_t* candidates, float* lane_kernel_ms, uint32_t* overflow_lanes,
+                       uint64_t* slot_words, void* stream) {
   if (!ws) return CL_ERR_INVALID_ARG;
   hipStream_t s = as_stream(stream);
   WsHeader back{};
@@ -600,6 +608,7 @@ cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments
   if (candidates) *candidates = back.total_cand;
   if (lane_kernel_ms) *lane_kernel_ms = back.lane_ms;
   if (overflow_lanes) *overflow_lanes = back.overflow;
+  if (slot_words) *slot_words = back.total_words;
   if (back.status) return status_error(back.status);
   if (!back.planned) return CL_ERR_NOT_PLANNED;
   return CL_OK;

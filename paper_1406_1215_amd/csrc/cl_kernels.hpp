@@ -252,6 +252,7 @@ __global__ void k_reset_status(WsHeader* hdr) {
   if (threadIdx.x == 0) {
     hdr->status = 0;
     hdr->total_cand = 0;
+    hdr->total_words = 0;
   }
 }
 
@@ -382,10 +383,10 @@ struct NodeOut {
 __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
   GraphDesc* desc = hdr->desc;
   const uint32_t G = hdr->G;
-  uint64_t carry_nh = 0, carry_nl = 0, carry_cost = 0;
+  uint64_t carry_nh = 0, carry_nl = 0, carry_cost = 0, carry_seg = 0;
   for (uint32_t base = 0; base < G; base += blockDim.x) {
     const uint32_t g = base + threadIdx.x;
-    uint64_t nh = 0, nl = 0, cost = 0;
+    uint64_t nh = 0, nl = 0, cost = 0, sg = 0;
     if (g < G) {
       GraphDesc& d = desc[g];
       const uint64_t nr = d.u_end - d.u_begin;
@@ -407,15 +408,18 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
       if (d.policy == 2 && nseg > 0x80000000ull) atomicOr(&d.status, kStCapacity);
       d.L = L;
       d.NH = nh;
+      sg = nseg;
       cost = (L > 0) ? Z : 0;
       nl = (L + kLaneGroup - 1) / kLaneGroup * kLaneGroup;
       d.NL = nl;
     }
-    uint64_t tot_nh, tot_nl, tot_cost;
+    uint64_t tot_nh, tot_nl, tot_cost, tot_seg;
     const uint64_t ex_nh = block_exclusive<uint64_t>(nh, &tot_nh);
     const uint64_t ex_nl = block_exclusive<uint64_t>(nl, &tot_nl);
     (void)block_exclusive<uint64_t>(cost, &tot_cost);
+    (void)block_exclusive<uint64_t>(sg, &tot_seg);
     carry_cost += tot_cost;
+    carry_seg += tot_seg;
     if (g < G) {
       desc[g].hs_off = carry_nh + ex_nh;
       desc[g].lane_off = carry_nl + ex_nl;
@@ -427,6 +431,7 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
     hdr->total_nh = carry_nh;
     hdr->total_nl = carry_nl;
     hdr->total_cost = carry_cost;
+    hdr->total_seg = carry_seg;
     uint32_t st = 0;
     for (uint32_t g = 0; g < G; ++g) st |= desc[g].status;
     if (hdr->cap_nl != 0 && (carry_nh > hdr->cap_nh || carry_nl > hdr->cap_nl)) st |= kStCapacity;
@@ -807,19 +812,63 @@ struct WriteEmit {
   }
 };
 
-// One-pass output: the lane counts every kept edge and writes the first
-// `cap` of them into the unit's slot (64-byte aligned), staged like WriteEmit.
-struct SlotEmit {
-  WriteEmit wr;      // window = all slots (lo = 0); the unit writes [pos, hi)
-  uint32_t c;
-  bool over;         // an edge did not fit
+// One-pass output: the lane counts every kept edge and writes the unit's
+// edges into its slot as 32-bit words: v for each edge, preceded by the pair
+// (kSourceMark, u) whenever the source changes (a vertex id is at most
+// 2^32 - 2, so kSourceMark is never a v).  Half the bytes of (u, v) pairs; the
+// compaction expands them.  Words are staged in LDS like WriteEmit and stored
+// as whole 64-byte chunks (16 words).  Words beyond the slot are counted, not
+// written; the unit then overflowed and the write kernel replays it.
+constexpr uint32_t kSourceMark = 0xFFFFFFFFu;
+constexpr int kWordSlots = 16;   // words per 64-byte chunk
+
+struct WordEmit {
+  uint32_t* stage;      // LDS, kWordSlots x kLaneThreads words (the pair stage's bytes)
+  gout<uint32_t> out;   // all slots, word-indexed
+  uint64_t start, pos, hi;  // the unit's slot [start, hi), next word position
+  uint32_t run;         // words staged by this unit (saturates at kWordSlots)
+  uint32_t cur;         // source of the last edge (kSourceMark: none yet)
+  uint32_t c;           // edges
+  uint64_t words;       // words the unit needs (its slot holds min(words, hi - start))
+  __device__ bool over() const { return words > hi - start; }
+  __device__ uint32_t& slot(uint64_t q) { return stage[(q & (kWordSlots - 1)) * kLaneThreads + threadIdx.x]; }
+  __device__ void flush(uint64_t qend, uint32_t own) {
+    const uint64_t q0 = (qend - 1) & ~static_cast<uint64_t>(kWordSlots - 1);
+    if (own == kWordSlots) {
+      gout<u32x4> dst = reinterpret_cast<gout<u32x4>>(out + q0);
+#pragma unroll
+      for (int i = 0; i < kWordSlots / 4; ++i)
+        dst[i] = u32x4{stage[(4 * i) * kLaneThreads + threadIdx.x], stage[(4 * i + 1) * kLaneThreads + threadIdx.x],
+                       stage[(4 * i + 2) * kLaneThreads + threadIdx.x], stage[(4 * i + 3) * kLaneThreads + threadIdx.x]};
+    } else {
+      for (uint64_t q = qend - own; q < qend; ++q) out[q] = slot(q);
+    }
+  }
+  __device__ void push(uint32_t x) {
+    ++words;
+    if (pos >= hi) return;
+    slot(pos) = x;
+    if (run < kWordSlots) ++run;
+    if ((pos & (kWordSlots - 1)) == kWordSlots - 1) {
+      flush(pos + 1, run);
+      run = kWordSlots;
+    }
+    ++pos;
+  }
   __device__ bool operator()(uint32_t u, uint32_t v) {
     ++c;
-    if (wr.pos < wr.hi)
-      wr(u, v);
-    else
-      over = true;
+    if (u != cur) {
+      push(kSourceMark);
+      push(u);
+      cur = u;
+    }
+    push(v);
     return true;
+  }
+  // the unit's last, incomplete chunk
+  __device__ void finish() {
+    const uint32_t part = static_cast<uint32_t>(pos & (kWordSlots - 1));
+    if (part) flush(pos, (run < part) ? run : part);
   }
 };
 
@@ -847,7 +896,7 @@ struct DegEmit {
 
 template <int kMode>
 struct EmitOf {
-  using type = SlotEmit;
+  using type = WordEmit;
 };
 template <>
 struct EmitOf<3> {
@@ -896,7 +945,8 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
   const gptr<uint64_t> slot_off = to_global(uniptr(hdr->slot_off));
   const gptr<uint64_t> lane_pos = to_global(uniptr(hdr->lane_pos));
   const gptr<uint32_t> group_graph = to_global(uniptr(hdr->group_graph));
-  const gout<uint2> slots = to_global_mut(uniptr_mut(hdr->slots));
+  const gout<uint32_t> slots = to_global_mut(uniptr_mut(hdr->slots));
+  const gout<uint32_t> lane_words = to_global_mut(uniptr_mut(hdr->lane_words));
   const gout<uint2> outw = to_global_mut(uniptr_mut(out));
   unsigned int* overflow = &hdr->overflow;
 
@@ -915,6 +965,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
   uint32_t unit = kNone;
   bool touched = false;      // write pass: the unit writes into the window
   uint32_t visits = 0;
+  uint64_t words_acc = 0;    // one pass: slot words of the lane's units
   LaneRun s{};
   s.sg = 0;
   s.sg_end = 0;
@@ -928,9 +979,11 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
       if constexpr (kMode == 0) {
         lane_cnt[unit] = em.c;
       } else if constexpr (kMode == 2) {
-        em.wr.finish();
+        em.finish();
         lane_cnt[unit] = em.c;
-        if (em.over) atomicAdd(overflow, 1u);
+        lane_words[unit] = static_cast<uint32_t>(em.words);
+        words_acc += em.words;
+        if (em.over()) atomicAdd(overflow, 1u);
       } else if constexpr (kMode == 3) {
         em.flush();
       } else {
@@ -985,16 +1038,15 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
           } else if constexpr (kMode == 2) {
             const uint64_t s0 = slot_off[unit];
             const uint64_t s1 = slot_off[unit + 1];
-            em.wr = WriteEmit{stage, slots, 0ull, s0, s1, 0u};
-            em.c = 0u;
-            em.over = false;
+            em = WordEmit{reinterpret_cast<uint32_t*>(stage), slots, s0, s0, s1, 0u, kSourceMark, 0u, 0ull};
           } else if constexpr (kMode == 3) {
             em = DegEmit{degp, kNone, 0u};
           } else {
             const uint64_t pos0 = lane_pos[unit];
             const uint64_t cnt = lane_cnt[unit];
             touched = (pos0 < e_hi) && (pos0 + cnt > e_lo);
-            if (only_overflow) touched = touched && (cnt > slot_off[unit + 1] - slot_off[unit]);
+            // one-pass plans: only the units whose words did not fit their slot
+            if (only_overflow) touched = touched && (lane_words[unit] > slot_off[unit + 1] - slot_off[unit]);
             em = WriteEmit{stage, outw, e_lo, pos0, e_hi, 0u};
             if (!touched) s.sg_end = s.sg;
           }
@@ -1016,25 +1068,31 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
     if (lane == 0)
       atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->total_cand), static_cast<unsigned long long>(visited));
   }
+  if (kMode == 2) {
+    for (int dd = 32; dd >= 1; dd >>= 1) words_acc += shfl_idx64(words_acc, lane ^ dd);
+    if (lane == 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->total_words), static_cast<unsigned long long>(words_acc));
+  }
 }
 // --------------------------------------------------------------------------
 // one-pass slots: capacity of a lane = its plan cost mu (in expected
-// candidates, which bounds its expected edges) + 8 sqrt(mu) + 24, rounded up
-// to whole 64-byte chunks; a lane above it (probability < 1e-14 by the
-// Chernoff bound used in Sec. 4, Theorem 2) is replayed by the write kernel.
+// candidates, which bounds its expected edges) + 8 sqrt(mu) + 24 edge words,
+// plus two words per segment for the source marks, rounded up to whole
+// 64-byte chunks; a lane above it (probability < 1e-14 by the Chernoff bound
+// used in Sec. 4, Theorem 2) is replayed by the write kernel.
 // --------------------------------------------------------------------------
 struct SlotIn {
   const WsHeader* hdr;
   struct Ctx {
     uint64_t nl;        // lanes of all graphs (padded)
-    uint64_t lane_off, L, Z;
+    uint64_t lane_off, L, Z, nseg;
   };
   __device__ uint32_t graph_of(uint64_t l) const {
     return (l < hdr->total_nl) ? hdr->group_graph[l / kLaneGroup] : 0u;
   }
   __device__ Ctx context(uint32_t g) const {
     const GraphDesc& d = hdr->desc[g];
-    return Ctx{hdr->total_nl, d.lane_off, d.L, d.C1 - d.C0};
+    return Ctx{hdr->total_nl, d.lane_off, d.L, d.C1 - d.C0, d.SB1 - d.SB0};
   }
   __device__ uint64_t load(uint64_t l, const Ctx& c) const {
     if (l >= c.nl) return 0;
@@ -1044,8 +1102,11 @@ struct SlotIn {
     const uint64_t c0 = hdr->lane_cum[l];
     const double mu = static_cast<double>(c1 > c0 ? c1 - c0 : 0) / static_cast<double>(kCostUnit);
     const double cap = (hdr->slot_margin == 1) ? mu : (mu + 8.0 * sqrt(mu) + 24.0);
-    const uint64_t cc = static_cast<uint64_t>(ceil(cap));
-    return (cc + kStageSlots - 1) / kStageSlots * kStageSlots;
+    // words: one per edge, plus a (mark, u) pair per source, at most one per segment
+    const uint64_t g0 = hdr->lane_seg[l];
+    const uint64_t g1 = (i + 1 < c.L) ? hdr->lane_seg[l + 1] : c.nseg;
+    const uint64_t cc = static_cast<uint64_t>(ceil(cap)) + 2 * (g1 > g0 ? g1 - g0 : 0);
+    return (cc + kWordSlots - 1) / kWordSlots * kWordSlots;
   }
 };
 
@@ -1058,42 +1119,70 @@ __global__ void k_slot_check(WsHeader* hdr) {
   if (hdr->slot_off[hdr->total_nl] > hdr->slot_cap) atomicOr(&hdr->status, kStCapacity);
 }
 
-// copies every lane's slot to its place in the output window [lo, hi); one
-// wavefront per 64 lanes, 64 edges per step
+// Expands every unit's slot words into (u, v) pairs at the unit's place in
+// the output window [lo, hi).  One wavefront per group of 64 units, the units
+// one after another, up to 256 words per step (four loads in flight per lane).
+// Inside a step a lane learns from ballots whether its word is a mark, a
+// source id (the word after a mark) or an edge, takes u from the nearest
+// source id at or below it (or the one carried from the previous step), and
+// writes its edge at the unit's position plus the number of edges before it.
+// Units whose slot overflowed are skipped here: the replay writes them.
 __global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out, uint64_t lo, uint64_t hi) {
   if (hdr->status || hdr->mode != 1 || !hdr->planned) return;
   const uint64_t ngroups = uni64(hdr->total_nl) / kLaneGroup;
   const int lane = threadIdx.x & 63;
+  const uint64_t below = (1ull << lane) - 1;       // lanes under this one
+  const uint64_t upto = below | (1ull << lane);    // lanes up to this one
   const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (blockDim.x / 64);
-  gptr<uint64_t> slots = to_global(uniptr(reinterpret_cast<const uint64_t*>(hdr->slots)));
+  gptr<uint32_t> slots = to_global(uniptr(static_cast<const uint32_t*>(hdr->slots)));
   const gout<uint64_t> out64 = to_global_mut(uniptr_mut(reinterpret_cast<uint64_t*>(out)));
   for (uint64_t grp = uni64(static_cast<uint64_t>(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6));
        grp < ngroups; grp += nwaves) {
     const uint64_t l = grp * kLaneGroup + lane;
     const uint64_t my_pos = hdr->lane_pos[l];
     const uint64_t my_cnt = hdr->lane_cnt[l];
+    const uint64_t my_words = hdr->lane_words[l];
     const uint64_t my_s0 = hdr->slot_off[l];
     const uint64_t my_cap = hdr->slot_off[l + 1] - my_s0;
     for (int j = 0; j < 64; ++j) {
       const uint64_t pos = uni64(shfl_idx64(my_pos, j));
       const uint64_t cnt = uni64(shfl_idx64(my_cnt, j));
+      const uint64_t words = uni64(shfl_idx64(my_words, j));
       const uint64_t s0 = uni64(shfl_idx64(my_s0, j));
       const uint64_t cap = uni64(shfl_idx64(my_cap, j));
-      if (cnt == 0 || cnt > cap || pos >= hi || pos + cnt <= lo) continue;
-      const uint64_t a = (pos > lo) ? pos : lo;
-      const uint64_t b = (pos + cnt < hi) ? pos + cnt : hi;
-      // 256 edges per step: four independent loads in flight per lane
-      for (uint64_t e0 = a; e0 < b; e0 += 256) {
-        uint64_t x[4];
+      if (cnt == 0 || words > cap || pos >= hi || pos + cnt <= lo) continue;
+      uint32_t carry_u = 0;
+      bool carry_mark = false;
+      uint64_t epos = pos;   // output position of the next edge
+      for (uint64_t w0 = 0; w0 < words; w0 += 256) {
+        uint32_t x[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const uint64_t e = e0 + r * 64 + lane;
-          if (e < b) x[r] = slots[s0 + (e - pos)];
+          const uint64_t idx = w0 + r * 64 + lane;
+          x[r] = (idx < words) ? slots[s0 + idx] : 0u;
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const uint64_t e = e0 + r * 64 + lane;
-          if (e < b) out64[e - lo] = x[r];
+          const bool valid = w0 + r * 64 + lane < words;
+          const bool mark = valid && x[r] == kSourceMark;
+          const uint64_t mmask = __ballot(mark);
+          const bool after_mark = (lane == 0) ? carry_mark : ((mmask >> (lane - 1)) & 1ull) != 0;
+          const bool is_u = valid && after_mark;
+          const bool edge = valid && !mark && !is_u;
+          const uint64_t umask = __ballot(is_u);
+          const uint64_t emask = __ballot(edge);
+          const uint64_t mine = umask & upto;
+          const uint32_t u_here = static_cast<uint32_t>(
+              __shfl(static_cast<int>(x[r]), mine ? 63 - __clzll(static_cast<long long>(mine)) : 0, 64));
+          const uint32_t u = mine ? u_here : carry_u;
+          const uint64_t e = epos + static_cast<uint64_t>(__popcll(emask & below));
+          if (edge && e >= lo && e < hi) out64[e - lo] = (static_cast<uint64_t>(x[r]) << 32) | u;
+          if (umask) {
+            const int top = 63 - __clzll(static_cast<long long>(umask));
+            carry_u = static_cast<uint32_t>(__shfl(static_cast<int>(x[r]), top, 64));
+          }
+          carry_mark = (mmask >> 63) != 0;
+          epos += static_cast<uint64_t>(__popcll(emask));
         }
       }
     }

@@ -80,10 +80,11 @@ struct WsHeader {
   uint32_t* group_graph; // [cap_nl / 64]
   // one-pass mode: every lane writes into its own slot while it counts
   uint64_t* lane_cum;    // [cap_nl + 1] cumulative plan cost at each lane's first segment
-  uint64_t* slot_off;    // [cap_nl + 1] exclusive prefix of the slot capacities (edges)
+  uint64_t* slot_off;    // [cap_nl + 1] exclusive prefix of the slot capacities (words)
   uint64_t* slot_scan_tmp;
-  uint2* slots;          // [slot_cap] edge pairs
-  uint64_t slot_cap;     // capacity of slots (edges)
+  uint32_t* slots;       // [slot_cap] words: v per edge, (mark, u) where the source changes
+  uint32_t* lane_words;  // [cap_nl] words each lane needed
+  uint64_t slot_cap;     // capacity of slots (words)
   uint32_t mode;         // 0: count then replay; 1: one pass into slots, then compaction
   uint32_t overflow;     // lanes whose edges exceeded their slot (replayed by the write kernel)
   uint32_t slot_margin;  // 0: mu + 8 sqrt(mu) + 24; 1: no margin
@@ -91,7 +92,9 @@ struct WsHeader {
   uint64_t total_cost;   // sum of the graphs' plan costs (cost units)
   // device-written totals
   uint64_t total_nh, total_nl, total_m;
+  uint64_t total_seg;   // segments of all graphs
   uint64_t total_cand;  // candidates visited by the count pass
+  uint64_t total_words; // slot words the one pass needed
   uint32_t status;
   uint32_t queue;
   uint32_t planned;   // 1 after a successful count
