@@ -5,8 +5,10 @@ A step is one pass of the whole generation path over the n = 1e7 power-law
 workload (exponent 2.1, w_min = 10, weights capped at sqrt(S), Philox seed 2),
 inputs resident in HBM: exact sum S, plan (validation, quantised prefix,
 segments, lane plan), one pass of every lane into its slot (counting and
-writing), offsets, compaction of the slots into the contiguous edge list.
-`value` is edges generated per second.  Printed as one JSON line, with:
+writing), offsets, compaction of the slots into the contiguous edge list
+(after the first step, which allocates the output, plan + one pass +
+compaction are one call, cl_sample_into).  `value` is edges generated per
+second.  Printed as one JSON line, with:
 
 * roofline: the one-pass generation kernel (Alg. 1 per lane, edges staged
   into 64-byte chunks of per-lane slots), timed with HIP events on its stream.
@@ -139,9 +141,15 @@ def main():
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
 
-    def step():
+    def step(fused=True):
+        """One step; with an output buffer from an earlier step, the plan, the
+        one pass and the expansion run in one call (cl_sample_into)."""
         nonlocal edges, plan
         S = cg.cl_weight_sum(w)
+        if fused and edges is not None:
+            plan, fits = cg.cl_sample_into([cg.Task(w, S, seed)], edges, ws=plan.ws)
+            if fits:
+                return plan.total
         plan = cg.cl_sample([cg.Task(w, S, seed)], ws=plan.ws if plan is not None else None)
         m = plan.total
         if args.verbose:
@@ -170,7 +178,7 @@ def main():
     # back costs a host round trip per step)
     copy_ms, lane_ms = [], []
     for _ in range(max(3, min(args.steps, 10))):
-        step()
+        step(fused=False)
         ev1.synchronize()
         copy_ms.append(ev0.elapsed_time(ev1))
         lane_ms.append(cg.cl_plan_info(plan)["lane_kernel_ms"])

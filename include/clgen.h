@@ -140,15 +140,34 @@ cl_status cl_count(const cl_graph* g /* host, G entries */, uint32_t G, const cl
 /* ---------------------------------------------------------------------------
  * Generation in one pass: the same plan as cl_count, then every lane runs
  * Alg. 1 once, counting its edges and writing them into its own slot of the
- * workspace (capacity from the lane's plan cost mu: mu + 8 sqrt(mu) + 24, a
- * Chernoff margin after Sec. 4, Theorem 2; a lane above it is replayed by
- * cl_generate).  m_out as for cl_count.  cl_generate then copies the slots to
- * the output instead of replaying the lanes.  The workspace is larger than
- * for cl_count by about 1.4 x 8 bytes per expected edge.  Synchronises twice.
+ * workspace as 32-bit words (v per edge, a mark and u where the source
+ * changes; capacity from the lane's plan cost mu: mu + 8 sqrt(mu) + 24 edge
+ * words, a Chernoff margin after Sec. 4, Theorem 2, plus two words per
+ * segment; a lane above it is replayed by cl_generate).  m_out as for
+ * cl_count.  cl_generate then expands the slots into the output instead of
+ * replaying the lanes.  The workspace is larger than for cl_count by about
+ * 1.5 x 4 bytes per expected edge.  Synchronises twice.
  * ------------------------------------------------------------------------- */
 cl_status cl_sample(const cl_graph* g /* host, G entries */, uint32_t G, const cl_tuning* t,
                     void* ws, uint64_t ws_bytes, uint64_t* m_out /* host */,
                     uint64_t* ws_required /* host, may be NULL */, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * cl_sample followed by cl_generate(ws, t, edges, 0, cap, graph_offsets)
+ * without returning to the host in between: for callers that already hold
+ * an output buffer (e.g. from an earlier run of the same shape).  The plan's
+ * second half, the one pass, the expansion into edges and graph_offsets are
+ * queued together; like cl_sample the call synchronises twice (sizes after
+ * the plan's first half, counts at the end), with no host round trip between
+ * the one pass and the expansion.  Returns
+ * CL_ERR_CAPACITY when the total m exceeds cap: m_out is set, edges holds the
+ * first cap edges and the plan stays valid for cl_generate with a larger
+ * buffer.  Other arguments and errors as for cl_sample and cl_generate.
+ * ------------------------------------------------------------------------- */
+cl_status cl_sample_into(const cl_graph* g /* host, G entries */, uint32_t G, const cl_tuning* t,
+                         void* ws, uint64_t ws_bytes, uint32_t* edges, uint64_t cap,
+                         uint64_t* graph_offsets, uint64_t* m_out /* host */,
+                         uint64_t* ws_required /* host, may be NULL */, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Generation, write pass: for a plan of cl_count, replays the planned lanes
@@ -191,7 +210,8 @@ cl_status cl_degrees(void* ws, const cl_tuning* t, uint32_t* deg, uint64_t deg_l
  * lanes includes the padding to whole wavefronts; candidates is the number of
  * candidates the lane kernel visited (the "edges + sources" work of Eq. 2-4,
  * rejections included); lane_kernel_ms is the duration of that kernel
- * (count pass or one pass), timed by HIP events on the caller's stream;
+ * (count pass or one pass), timed by HIP events on the caller's stream and
+ * stored on that stream after the planning call returns (read it there);
  * overflow_lanes counts one-pass lanes that exceeded their slot; slot_words
  * is the number of 32-bit words the one pass needed for its slots (one per
  * edge plus two per change of source inside a lane; 0 for other plans). */

@@ -70,6 +70,8 @@ def lib():
                                   _U64P, _U64P]),
         "cl_sample": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _U64, _U64P,
                           _U64P, _P]),
+        "cl_sample_into": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _U64, _P,
+                               _U64, _P, _U64P, _U64P, _P]),
         "cl_count": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _U64, _U64P,
                          _U64P, _P]),
         "cl_generate": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _U64, _P, _P]),
@@ -207,7 +209,7 @@ def _graph_array(tasks: Sequence[Task]):
     return arr
 
 
-def _plan(fn_name: str, one_pass: int, tasks: Sequence[Task], tuning, ws, stream) -> Plan:
+def _plan(fn_name: str, one_pass: int, tasks: Sequence[Task], tuning, ws, stream, into=None) -> Plan:
     L = lib()
     tasks = list(tasks)
     arr = _graph_array(tasks)
@@ -228,6 +230,10 @@ def _plan(fn_name: str, one_pass: int, tasks: Sequence[Task], tuning, ws, stream
     fn = getattr(L, fn_name)
     if fn_name == "cl_plan":   # no edge counts
         call = lambda: fn(arr, G, tun, _ptr(ws), ws.numel(), ctypes.byref(req), _stream(stream))
+    elif fn_name == "cl_sample_into":
+        edges, cap, offs = into
+        call = lambda: fn(arr, G, tun, _ptr(ws), ws.numel(), _ptr(edges), int(cap), _ptr(offs), m,
+                          ctypes.byref(req), _stream(stream))
     else:
         call = lambda: fn(arr, G, tun, _ptr(ws), ws.numel(), m, ctypes.byref(req), _stream(stream))
     code = call()
@@ -236,8 +242,12 @@ def _plan(fn_name: str, one_pass: int, tasks: Sequence[Task], tuning, ws, stream
             break
         ws = _ws(req.value, dev)
         code = call()
+    plan = Plan(ws=ws, graphs=arr, tasks=tasks, m=[int(x) for x in m], tuning=tuning)
+    if into is not None and code == -7:   # the edges did not fit: m is known, the plan is kept
+        plan.keep.append("over_capacity")
+        return plan
     _check(code, fn_name)
-    return Plan(ws=ws, graphs=arr, tasks=tasks, m=[int(x) for x in m], tuning=tuning)
+    return plan
 
 
 def cl_count(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional[torch.Tensor] = None,
@@ -251,6 +261,20 @@ def cl_sample(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional
     """Plans the tasks and generates them in one pass into per-lane slots of
     the workspace; cl_generate then copies the slots to the output."""
     return _plan("cl_sample", 1, tasks, tuning, ws, stream)
+
+
+def cl_sample_into(tasks: Sequence[Task], edges: torch.Tensor, cap: Optional[int] = None,
+                   graph_offsets: Optional[torch.Tensor] = None, tuning: Optional[dict] = None,
+                   ws: Optional[torch.Tensor] = None, stream=None):
+    """cl_sample and cl_generate(plan, edges, 0, cap) in one call (no host
+    round trip in between).  Returns (plan, fits): when the edges do not fit
+    (plan.total > cap), edges hold the first cap of them and cl_generate
+    with a larger buffer completes the output from the same plan."""
+    if cap is None:
+        cap = edges.numel() // 2
+    assert edges.dtype == torch.int32 and edges.is_contiguous() and edges.numel() >= 2 * cap
+    plan = _plan("cl_sample_into", 1, tasks, tuning, ws, stream, into=(edges, cap, graph_offsets))
+    return plan, "over_capacity" not in plan.keep
 
 
 def cl_plan(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional[torch.Tensor] = None,

@@ -422,8 +422,18 @@ cl_status cl_workspace_size(const cl_graph* g, uint32_t G, const cl_tuning* t, u
   return CL_OK;
 }
 
+// mode 0: plan + count pass; 1: plan + one pass into slots; 2: plan only.
+// With `into` (mode 1), the expansion into edges[0, cap) and graph_offsets is
+// queued before the final read-back.
+struct IntoOut {
+  uint32_t* edges;
+  uint64_t cap;
+  uint64_t* graph_offsets;
+};
+
 static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes,
-                             uint64_t* m_out, uint64_t* ws_required, void* stream, uint32_t mode) {
+                             uint64_t* m_out, uint64_t* ws_required, void* stream, uint32_t mode,
+                             const IntoOut* into = nullptr) {
   cl_status st = check_graphs(g, G);
   if (st != CL_OK) return st;
   if (!m_out) return CL_ERR_INVALID_ARG;
@@ -526,7 +536,16 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
     ev0 = nullptr;
     ev1 = nullptr;
   }
-  const hipError_t eb = launch_plan_back(dhdr, h, t, s, ev0, ev1);
+  // planned: 1 = counted (cl_count, cl_sample), 2 = plan only (cl_plan); set
+  // on the stream after the lane kernel (the write kernels test it), and
+  // cleared again below if the plan failed
+  const uint32_t flag = (mode == 2) ? 2u : 1u;
+  hipError_t eb = launch_plan_back(dhdr, h, t, s, ev0, ev1);
+  if (eb == hipSuccess) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->planned, flag);
+    eb = hipGetLastError();
+  }
+  if (eb == hipSuccess && into) eb = launch_write(dhdr, t, into->edges, 0, into->cap, into->graph_offsets, s);
   float lane_ms = -1.0f;
   if (eb == hipSuccess && hipMemcpyAsync(m_out, h.m_dev, 8ull * G, hipMemcpyDeviceToHost, s) == hipSuccess &&
       hipMemcpyAsync(&back, dhdr, sizeof(back), hipMemcpyDeviceToHost, s) == hipSuccess &&
@@ -539,12 +558,21 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
   if (eb != hipSuccess) return CL_ERR_DEVICE;
-  if (back.status) return status_error(back.status);
-  // planned: 1 = counted (cl_count, cl_sample), 2 = plan only (cl_plan)
-  const uint32_t flag = (mode == 2) ? 2u : 1u;
-  CL_TRY(hipMemcpyAsync(&dhdr->lane_ms, &lane_ms, sizeof(lane_ms), hipMemcpyHostToDevice, s));
-  CL_TRY(hipMemcpyAsync(&dhdr->planned, &flag, sizeof(flag), hipMemcpyHostToDevice, s));
-  CL_TRY(hipStreamSynchronize(s));
+  if (back.status) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->planned, 0u);
+    (void)hipGetLastError();
+    return status_error(back.status);
+  }
+  // the lane kernel's duration, stored by a kernel (no host buffer to keep alive)
+  uint32_t ms_bits;
+  memcpy(&ms_bits, &lane_ms, sizeof(ms_bits));
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, reinterpret_cast<uint32_t*>(&dhdr->lane_ms), ms_bits);
+  CL_TRY(hipGetLastError());
+  if (into) {
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < G; ++i) total += m_out[i];
+    if (total > into->cap) return CL_ERR_CAPACITY;
+  }
   return CL_OK;
 }
 
@@ -556,6 +584,14 @@ cl_status cl_count(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, 
 cl_status cl_sample(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes, uint64_t* m_out,
                     uint64_t* ws_required, void* stream) {
   return plan_common(g, G, t, ws, ws_bytes, m_out, ws_required, stream, 1u);
+}
+
+cl_status cl_sample_into(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes,
+                         uint32_t* edges, uint64_t cap, uint64_t* graph_offsets, uint64_t* m_out,
+                         uint64_t* ws_required, void* stream) {
+  if (cap > 0 && !edges) return CL_ERR_INVALID_ARG;
+  const IntoOut into{edges, cap, graph_offsets};
+  return plan_common(g, G, t, ws, ws_bytes, m_out, ws_required, stream, 1u, &into);
 }
 
 cl_status cl_plan(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes,

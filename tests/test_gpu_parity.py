@@ -310,3 +310,38 @@ def test_one_pass_slot_overflow_replay(cg, tuning):
     got, plan = _gpu_edges(cg, w, S, 5, tuning=tuning, planner="cl_sample")
     assert plan.m == [m]
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("tuning", [None, {"slot_margin": 1}])
+def test_sample_into_one_call(cg, tuning):
+    """cl_sample_into: plan, one pass and expansion into the caller's buffer in
+    one call.  Bit-exact with the oracle for a batch (graph offsets included,
+    and with the overflow replay when slots have no margin); a buffer that is
+    too small holds the first cap edges and the plan completes the output
+    through cl_generate; a second call reuses workspace and buffer."""
+    import torch
+    ws_ = [_heavy(20000, 90, 30.0), W.config_small(), np.zeros(3), _heavy(5000, 91, 60.0)]
+    tasks, wants = [], []
+    for i, w in enumerate(ws_):
+        S = O.exact_sum(w) if O.exact_sum(w) > 0 else 1.0
+        wants.append(O.generate(w, S, 300 + i)[0])
+        tasks.append(cg.Task(_to_dev(w), S, 300 + i))
+    want = np.concatenate(wants)
+    m = want.shape[0]
+    edges = torch.full((m + 100, 2), -1, dtype=torch.int32, device="cuda:0")
+    go = torch.zeros(len(tasks) + 1, dtype=torch.int64, device="cuda:0")
+    plan, fits = cg.cl_sample_into(tasks, edges, cap=m + 100, graph_offsets=go, tuning=tuning)
+    assert fits and plan.total == m
+    assert np.array_equal(_edges_np(edges)[:m], want)
+    off = go.cpu().numpy()
+    assert list(np.diff(off)) == [x.shape[0] for x in wants]
+    # too small: the first cap edges, then the rest from the same plan
+    small = torch.zeros((m // 3, 2), dtype=torch.int32, device="cuda:0")
+    plan2, fits2 = cg.cl_sample_into(tasks, small, tuning=tuning, ws=plan.ws)
+    assert not fits2 and plan2.total == m
+    assert np.array_equal(_edges_np(small), want[: m // 3])
+    assert np.array_equal(_edges_np(cg.cl_generate(plan2))[:m], want)
+    # the same buffer and workspace again
+    edges.fill_(-1)
+    plan3, fits3 = cg.cl_sample_into(tasks, edges, tuning=tuning, ws=plan.ws)
+    assert fits3 and np.array_equal(_edges_np(edges)[:m], want)
