@@ -636,9 +636,6 @@ __device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_
 __device__ __forceinline__ uint64_t uni64(uint64_t x) {
   return (static_cast<uint64_t>(uni32(static_cast<uint32_t>(x >> 32))) << 32) | uni32(static_cast<uint32_t>(x));
 }
-__device__ __forceinline__ double unif64(double x) {
-  return __longlong_as_double(static_cast<long long>(uni64(static_cast<uint64_t>(__double_as_longlong(x)))));
-}
 template <class T>
 __device__ __forceinline__ const T* uniptr(const T* p) {
   return reinterpret_cast<const T*>(uni64(reinterpret_cast<uint64_t>(p)));
@@ -895,7 +892,9 @@ struct DegEmit {
 };
 
 template <int kMode>
-struct EmitOf {
+struct EmitOf;
+template <>
+struct EmitOf<2> {
   using type = WordEmit;
 };
 template <>
@@ -913,7 +912,7 @@ struct EmitOf<1> {
 
 // The lane kernel.  kMode 0: count pass.  kMode 1: write pass (replay into
 // the output window; in one-pass plans only the units that overflowed their
-// slot).  kMode 2: one pass, count and write into slots.  kMode 3: degrees
+// slot).  kMode 2: one pass, count and write slot words.  kMode 3: degrees
 // only (adds into deg at each graph's node offset q_off; no edge output).
 //
 // Scheduling: the work units of the lane plan (Eq. 5 applied to lanes) are
