@@ -151,3 +151,15 @@ def test_round_robin_refused_where_edges_are_written(cg, planner):
         getattr(cg, planner)([cg.Task(_dev(w), S, 1)], tuning={"partition": 2})
     with pytest.raises(cg.ClError):
         cg.cl_plan([cg.Task(_dev(w), S, 1)], tuning={"partition": 3})
+
+
+@pytest.mark.parametrize("n", [1, 7, 1000, 4095, 4096, 4097, 70000])
+def test_degrees_single_graph_sizes(cg, n):
+    """One graph of sizes from a single node to several units' worth of
+    sources, bit-exact."""
+    w = W.powerlaw_capped(n, 2.2, 3.0, np.random.default_rng(n)) if n > 1 else np.array([5.0])
+    S = O.exact_sum(w)
+    want, _ = _oracle_degrees(w, S, 40 + n)
+    plan = cg.cl_plan([cg.Task(_dev(w), S, 40 + n)])
+    (deg,) = cg.cl_degrees(plan)
+    assert np.array_equal(deg.cpu().numpy().view(np.uint32).astype(np.int64), want)
