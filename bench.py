@@ -96,6 +96,9 @@ def parse():
     ap.add_argument("--full-graph-degrees", action="store_true",
                     help="instead of the step: the degree sequence of the whole n=1e9 graph (exponent 2.1, mean "
                          "degree 500), every edge generated and consumed on the fly, part by part")
+    ap.add_argument("--full-graph-edges", action="store_true",
+                    help="instead of the step: every edge of the whole n=1e9 graph written to device memory part "
+                         "by part (one reused buffer) and digested")
     ap.add_argument("--parts", type=int, default=64)
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000, help="sources of the plain workload")
@@ -126,7 +129,7 @@ def main():
     cg.lib()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    if args.full_graph_degrees:
+    if args.full_graph_degrees or args.full_graph_edges:
         print(json.dumps(bench_full_graph(args, cg, W, torch, np, dev)), flush=True)
         return
 
@@ -281,7 +284,9 @@ def main():
 def bench_full_graph(args, cg, W, torch, np, dev):
     """The paper's largest power-law shape (1e9 nodes, mean degree 500) on one
     GPU: all edges generated part by part (uniform consecutive partition) and
-    reduced to the degree sequence; checked against E[m] and Var[m]."""
+    either reduced to the degree sequence (--full-graph-degrees) or written
+    to device memory, part after part into one buffer, and digested
+    (--full-graph-edges); m checked against E[m] and Var[m]."""
     from paper_1406_1215_amd import parts
     log("bench: generating the n=1e9 weights")
     w_np = W.config_share()
@@ -291,17 +296,28 @@ def bench_full_graph(args, cg, W, torch, np, dev):
     Em, Vm = cg.cl_expected_edges(w, S)
     log(f"bench: S = {S:.6g}, E[m] = {Em:.6g}; {args.parts} parts")
     seed = 3
-    parts.degrees(w[: 1 << 20].contiguous(), float(w[: 1 << 20].sum().item()), seed, 2)   # warm-up (small)
-    res = parts.degrees(w, S, seed, args.parts, log=log if args.verbose else None)
+    tail = w[-(1 << 20):].contiguous()   # warm-up on the lightest 2^20 nodes (a sparse graph)
+    fn = parts.edges if args.full_graph_edges else parts.degrees
+    fn(tail, float(tail.sum().item()), seed, 2)
+    del tail
+    res = fn(w, S, seed, args.parts, log=log if args.verbose else None)
     m = res["edges"]
     z = (m - Em) / math.sqrt(Vm)
-    deg = res["deg"]
-    return {"metric": "edges/sec generated and reduced to degrees, whole graph", "value": m / res["seconds"],
-            "unit": "edges/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f64",
-            "config": {"workload": "power law, n=1e9, exponent 2.1, mean degree 500, cap sqrt(500 n), Philox seed 3",
-                       "parts": args.parts},
-            "edges": m, "seconds": res["seconds"], "expected_edges": Em, "z_score_of_m": z,
-            "max_degree": int(deg.max().item()), "isolated_nodes": int((deg == 0).sum().item())}
+    out = {"metric": ("edges/sec generated into device memory and digested, whole graph" if args.full_graph_edges
+                      else "edges/sec generated and reduced to degrees, whole graph"),
+           "value": m / res["seconds"], "unit": "edges/s", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "dtype": "f64",
+           "config": {"workload": "power law, n=1e9, exponent 2.1, mean degree 500, cap sqrt(500 n), Philox seed 3",
+                      "parts": args.parts},
+           "edges": m, "seconds": res["seconds"], "expected_edges": Em, "z_score_of_m": z}
+    if args.full_graph_edges:
+        out["digest"] = res["digest"]
+        out["largest_part_edges"] = res["largest_part"]
+    else:
+        deg = res["deg"]
+        out["max_degree"] = int(deg.max().item())
+        out["isolated_nodes"] = int((deg == 0).sum().item())
+    return out
 
 
 def bench_expdeg(cg, W, torch, dev, reps=5):

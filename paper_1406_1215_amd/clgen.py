@@ -209,7 +209,8 @@ def _graph_array(tasks: Sequence[Task]):
     return arr
 
 
-def _plan(fn_name: str, one_pass: int, tasks: Sequence[Task], tuning, ws, stream, into=None) -> Plan:
+def _plan(fn_name: str, one_pass: int, tasks: Sequence[Task], tuning, ws, stream, into=None,
+          ws_growth: float = 1.0) -> Plan:
     L = lib()
     tasks = list(tasks)
     arr = _graph_array(tasks)
@@ -240,7 +241,8 @@ def _plan(fn_name: str, one_pass: int, tasks: Sequence[Task], tuning, ws, stream
     for _ in range(2):   # a too small workspace: first the fixed part, then the data-dependent rest
         if code != -6:
             break
-        ws = _ws(req.value, dev)
+        ws = None   # release the old workspace before the larger one is allocated
+        ws = _ws(int(req.value * ws_growth), dev)
         code = call()
     plan = Plan(ws=ws, graphs=arr, tasks=tasks, m=[int(x) for x in m], tuning=tuning)
     if into is not None and code == -7:   # the edges did not fit: m is known, the plan is kept
@@ -265,7 +267,7 @@ def cl_sample(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional
 
 def cl_sample_into(tasks: Sequence[Task], edges: torch.Tensor, cap: Optional[int] = None,
                    graph_offsets: Optional[torch.Tensor] = None, tuning: Optional[dict] = None,
-                   ws: Optional[torch.Tensor] = None, stream=None):
+                   ws: Optional[torch.Tensor] = None, stream=None, ws_growth: float = 1.0):
     """cl_sample and cl_generate(plan, edges, 0, cap) in one call (no host
     round trip in between).  Returns (plan, fits): when the edges do not fit
     (plan.total > cap), edges hold the first cap of them and cl_generate
@@ -273,14 +275,15 @@ def cl_sample_into(tasks: Sequence[Task], edges: torch.Tensor, cap: Optional[int
     if cap is None:
         cap = edges.numel() // 2
     assert edges.dtype == torch.int32 and edges.is_contiguous() and edges.numel() >= 2 * cap
-    plan = _plan("cl_sample_into", 1, tasks, tuning, ws, stream, into=(edges, cap, graph_offsets))
+    plan = _plan("cl_sample_into", 1, tasks, tuning, ws, stream, into=(edges, cap, graph_offsets),
+                 ws_growth=ws_growth)
     return plan, "over_capacity" not in plan.keep
 
 
 def cl_plan(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional[torch.Tensor] = None,
-            stream=None) -> Plan:
+            stream=None, ws_growth: float = 1.0) -> Plan:
     """The plan alone (no lane kernel, no counts: plan.m is zeros), for cl_degrees."""
-    return _plan("cl_plan", 0, tasks, tuning, ws, stream)
+    return _plan("cl_plan", 0, tasks, tuning, ws, stream, ws_growth=ws_growth)
 
 
 def cl_generate(plan: Plan, edges: Optional[torch.Tensor] = None, edge_begin: int = 0, cap: Optional[int] = None,

@@ -163,3 +163,22 @@ def test_degrees_single_graph_sizes(cg, n):
     plan = cg.cl_plan([cg.Task(_dev(w), S, 40 + n)])
     (deg,) = cg.cl_degrees(plan)
     assert np.array_equal(deg.cpu().numpy().view(np.uint32).astype(np.int64), want)
+
+
+@pytest.mark.parametrize("nparts", [1, 3, 8])
+def test_whole_graph_edges_part_by_part(cg, nparts):
+    """parts.edges: every part generated into one reused buffer; the parts
+    concatenate to the oracle's edge list, and the position-keyed digest of
+    the whole list matches."""
+    from paper_1406_1215_amd import parts
+    w = W.config_plain(n=150_000)
+    S = O.exact_sum(w)
+    want, m, _, _ = O.generate(w, S, 12)
+    got = []
+    res = parts.edges(_dev(w), S, 12, nparts,
+                      consume=lambda e, first: got.append((first, e.cpu().numpy().view(np.uint32).copy())))
+    assert res["edges"] == m
+    assert [f for f, _ in got] == list(np.cumsum([0] + [x.shape[0] for _, x in got])[:-1])
+    assert np.array_equal(np.concatenate([x for _, x in got]), want)
+    res2 = parts.edges(_dev(w), S, 12, nparts)
+    assert res2["digest"] == O.hash_edges(want)
