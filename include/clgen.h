@@ -171,14 +171,16 @@ cl_status cl_sample_into(const cl_graph* g /* host, G entries */, uint32_t G, co
 
 /* ---------------------------------------------------------------------------
  * Generation, write pass: for a plan of cl_count, replays the planned lanes
- * with the same random words; for a plan of cl_sample, copies the lanes'
- * slots.  Either way it writes every edge whose position in the batch output lies in
+ * with the same random words; for a plan of cl_sample, expands the lanes'
+ * slot words (and replays the lanes whose slot overflowed).  Either way it
+ * writes every edge whose position in the batch output lies in
  * [edge_begin, edge_begin + cap) to edges[2 (pos - edge_begin) + {0,1}] as
  * (u, v).  Task g's edges occupy positions [off_g, off_g + m_g), off_g = sum of
  * m_h for h < g.  graph_offsets (device, G + 1 entries, may be NULL) receives
  * off_0..off_{G-1} and the total.  Writing the output in windows (slabs)
  * costs each window only the lanes that overlap it.  Asynchronous.
- * ws must hold the plan of a successful cl_count (same inputs, unchanged).
+ * ws must hold the plan of a successful cl_count, cl_sample or cl_sample_into
+ * (same inputs, unchanged).
  * ------------------------------------------------------------------------- */
 cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t edge_begin, uint64_t cap,
                       uint64_t* graph_offsets, void* stream);

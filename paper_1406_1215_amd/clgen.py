@@ -261,7 +261,7 @@ def cl_count(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional[
 def cl_sample(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional[torch.Tensor] = None,
               stream=None) -> Plan:
     """Plans the tasks and generates them in one pass into per-lane slots of
-    the workspace; cl_generate then copies the slots to the output."""
+    the workspace; cl_generate then expands the slots into the output."""
     return _plan("cl_sample", 1, tasks, tuning, ws, stream)
 
 
