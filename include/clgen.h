@@ -80,6 +80,10 @@ typedef struct cl_tuning {
                               contiguous in (u, v) order, so 2 is accepted by cl_plan only (then
                               cl_degrees); cl_count and cl_sample return CL_ERR_INVALID_ARG.
                               Other values: CL_ERR_INVALID_ARG. */
+  uint32_t tail_units;     /* with partition 0: 0 = graded (default): the last 1/8 of a graph's
+                              cost is cut into units 4 times smaller than lane_budget, so that the
+                              lanes still busy when the work runs out finish close together
+                              (graphs of at least 4096 units); 1 = uniform units */
 } cl_tuning;
 
 /* ---------------------------------------------------------------------------

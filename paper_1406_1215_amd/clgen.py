@@ -39,7 +39,7 @@ class cl_graph(ctypes.Structure):
 
 class cl_tuning(ctypes.Structure):
     _fields_ = [("lane_budget", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
-                ("slot_margin", ctypes.c_uint32), ("partition", ctypes.c_uint32)]
+                ("slot_margin", ctypes.c_uint32), ("partition", ctypes.c_uint32), ("tail_units", ctypes.c_uint32)]
 
 
 _lib = None
@@ -122,7 +122,8 @@ def _tuning(t: Optional[dict]):
     if t is None:
         return None
     return ctypes.pointer(cl_tuning(int(t.get("lane_budget", 0)), int(t.get("blocks_per_cu", 0)),
-                                    int(t.get("slot_margin", 0)), int(t.get("partition", 0))))
+                                    int(t.get("slot_margin", 0)), int(t.get("partition", 0)),
+                                    int(t.get("tail_units", 0))))
 
 
 def _f64(w: torch.Tensor) -> torch.Tensor:

@@ -409,7 +409,7 @@ cl_status cl_workspace_size(const cl_graph* g, uint32_t G, const cl_tuning* t, u
   double nl = 0.0, nh = 0.0, cost = 0.0, nseg = 0.0;
   for (uint32_t i = 0; i < G; ++i) {
     const double nr = static_cast<double>(g[i].u_end - g[i].u_begin);
-    nl += (g[i].S * 0.5 + 2.0 * nr) / static_cast<double>(bu) + kLaneGroup;
+    nl += 1.5 * (g[i].S * 0.5 + 2.0 * nr) / static_cast<double>(bu) + kLaneGroup;   // graded tail: up to +38 %
     nh += g[i].S / 256.0 + 64.0;
     nseg += g[i].S / 256.0 + 64.0 + nr;
     cost += kCostUnit * (g[i].S * 0.5 + 2.0 * nr);
@@ -462,6 +462,7 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
     d.r_off = ro;
     d.budget = bu;
     d.policy = policy;
+    d.graded = (t && t->tail_units == 1) ? 0u : 1u;
     qo += g[i].n + 1;
     ro += (g[i].u_end - g[i].u_begin) + 1;
     desc[i] = d;

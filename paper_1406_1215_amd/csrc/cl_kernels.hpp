@@ -394,12 +394,24 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
       const uint64_t Z = d.C1 - d.C0;
       const uint64_t nseg = d.SB1 - d.SB0;
       nh = (d.H > 0) ? (hdr->SB[d.r_off + d.H] - d.SB0) : 0;
-      uint64_t L = 0;
+      uint64_t L = 0, Lm = 0, Zm = Z;
       if (nr > 0 && d.qscale != 0.0 && d.status == 0) {
         L = (Z + d.budget - 1) / d.budget;
         if (L > nseg) L = nseg;
         if (d.policy == 1 && L > nr) L = nr;   // equal source counts: at most one unit per source
         if (L == 0) L = 1;
+        Lm = L;
+        const uint64_t bt = d.budget / kTailDiv;
+        if (d.policy == 0 && d.graded && L >= kTailMinUnits && bt > 0) {
+          const uint64_t Zt = Z / kTailShare;
+          const uint64_t m = (Z - Zt + d.budget - 1) / d.budget;
+          const uint64_t t = (Zt + bt - 1) / bt;
+          if (m > 0 && t > 0 && m + t <= nseg) {
+            Zm = Z - Zt;
+            Lm = m;
+            L = m + t;
+          }
+        }
       }
       // segment and unit indices are 32-bit: a graph above 2^32 - 1 segments
       // is refused (n < 2^32 sources leaves room for ~1e9 heavy segments)
@@ -407,6 +419,8 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
       // round-robin units step by L <= nseg: keep sg + L below 2^32
       if (d.policy == 2 && nseg > 0x80000000ull) atomicOr(&d.status, kStCapacity);
       d.L = L;
+      d.Lm = Lm;
+      d.Zm = Zm;
       d.NH = nh;
       sg = nseg;
       cost = (L > 0) ? Z : 0;
@@ -507,8 +521,9 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
 
 // --------------------------------------------------------------------------
 // lane plan.  Lane i of a graph starts at the first segment whose
-// inclusive cumulative cost reaches i Z / L (Eq. 5 with P = L lanes), where a
-// segment of source u carries cost c_u / K_u.
+// inclusive cumulative cost reaches T_i (Eq. 5 with P = L lanes), where a
+// segment of source u carries cost c_u / K_u; T_i = i Zm / Lm for i <= Lm and
+// Zm + (i - Lm) (Z - Zm) / (L - Lm) after (uniform units when Lm = L).
 // --------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t lane_floor(uint64_t C, uint64_t L, uint64_t Z) {
   return static_cast<uint64_t>(floor(static_cast<double>(C) * static_cast<double>(L) / static_cast<double>(Z)));
@@ -517,13 +532,23 @@ __device__ __forceinline__ uint64_t lane_floor(uint64_t C, uint64_t L, uint64_t 
 struct PlanCtx {
   const double* w;
   double S;
-  uint64_t r_off, nr, u_begin, L, Z, C0, SB0, lane_off;
+  uint64_t r_off, nr, u_begin, L, Z, C0, SB0, lane_off, Lm, Zm;
   uint32_t policy;
+  // the last unit whose start T_i is at most C (monotone in C)
+  __device__ uint64_t unit_of(uint64_t C) const {
+    if (C < Zm || Lm == L) return lane_floor(C, Lm, Zm);
+    return Lm + lane_floor(C - Zm, L - Lm, Z - Zm);
+  }
+  __device__ double start_of(uint64_t i) const {
+    if (i <= Lm) return static_cast<double>(i) * static_cast<double>(Zm) / static_cast<double>(Lm);
+    return static_cast<double>(Zm) +
+           static_cast<double>(i - Lm) * static_cast<double>(Z - Zm) / static_cast<double>(L - Lm);
+  }
 };
 
 __device__ __forceinline__ PlanCtx plan_ctx(const GraphDesc& d) {
-  return PlanCtx{d.w, d.S, d.r_off, d.u_end - d.u_begin, d.u_begin, d.L, d.C1 - d.C0, d.C0, d.SB0, d.lane_off,
-                 d.policy};
+  return PlanCtx{d.w,  d.S,         d.r_off, d.u_end - d.u_begin, d.u_begin, d.L, d.C1 - d.C0, d.C0, d.SB0,
+                 d.lane_off, d.Lm, d.Zm, d.policy};
 }
 
 __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
@@ -545,7 +570,6 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
     A[i] = d.w[d.u_begin + r] / d.S;  // a_u of Alg. 1, once per source
     if (d.L == 0 || d.policy == 2) continue;   // round-robin starts are set with the groups
     const uint64_t L = d.L;
-    const uint64_t Z = d.Z;
     const uint64_t cex = C[i] - d.C0;
     if (d.policy == 1) {
       // equal source counts: unit li starts at source floor(li nr / L), segment 0
@@ -558,15 +582,15 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
       continue;
     }
     const uint64_t cin = C[i + 1] - d.C0;
-    uint64_t ilo = (r == 0) ? 0 : lane_floor(cex, L, Z) + 1;
-    uint64_t ihi = lane_floor(cin, L, Z);
+    uint64_t ilo = (r == 0) ? 0 : d.unit_of(cex) + 1;
+    uint64_t ihi = d.unit_of(cin);
     if (ihi > L - 1) ihi = L - 1;
     if (ilo > ihi) continue;   // no unit starts at this source (most sources)
     const uint64_t sbi = SB[i];
     const uint64_t K = SB[i + 1] - sbi;
     const double cnode = static_cast<double>(cin - cex);
     for (uint64_t li = ilo; li <= ihi; ++li) {
-      const double Ti = static_cast<double>(li) * static_cast<double>(Z) / static_cast<double>(L);
+      const double Ti = d.start_of(li);
       double kk = ceil((Ti - static_cast<double>(cex)) * static_cast<double>(K) / cnode) - 1.0;
       if (!(kk > 0.0)) kk = 0.0;
       if (kk > static_cast<double>(K - 1)) kk = static_cast<double>(K - 1);
@@ -1119,72 +1143,99 @@ __global__ void k_slot_check(WsHeader* hdr) {
 }
 
 // Expands every unit's slot words into (u, v) pairs at the unit's place in
-// the output window [lo, hi).  One wavefront per group of 64 units, the units
-// one after another, up to 256 words per step (four loads in flight per lane).
-// Inside a step a lane learns from ballots whether its word is a mark, a
-// source id (the word after a mark) or an edge, takes u from the nearest
-// source id at or below it (or the one carried from the previous step), and
-// writes its edge at the unit's position plus the number of edges before it.
-// Units whose slot overflowed are skipped here: the replay writes them.
+// the output window [lo, hi).  One wavefront per group of 64 units, which it
+// reads as one stream: the words of the group's units one after the other
+// (units whose slot overflowed, or that miss the window, left out; the
+// replay writes the overflowed ones), 64 consecutive words per instruction
+// and kCompactSteps instructions in flight per lane, whatever the unit sizes.
+// Each unit's words begin with a mark and its source id, so the decoding runs
+// across unit boundaries unchanged: a lane learns from ballots whether its
+// word is a mark, a source id (the word after a mark) or an edge, takes u from
+// the nearest source id at or below it (or the one carried from the previous
+// instruction), and numbers its edge by the edges before it in the stream.
+// The unit of a word comes from the group's word prefix in LDS (a lane's
+// unit index only moves forward); edge k of the stream lies in unit j and
+// goes to position lane_pos[j] + (k - edges of the stream before unit j).
+constexpr int kCompactSteps = 4;
+
 __global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out, uint64_t lo, uint64_t hi) {
+  __shared__ uint64_t sh_wpre[4][kLaneGroup + 1];   // stream position of each unit's first word, then the total
+  __shared__ uint64_t sh_src[4][kLaneGroup];        // slot index of stream word t of unit j: sh_src[j] + t
+  __shared__ uint64_t sh_dst[4][kLaneGroup];        // output position of stream edge k of unit j: sh_dst[j] + k
   if (hdr->status || hdr->mode != 1 || !hdr->planned) return;
   const uint64_t ngroups = uni64(hdr->total_nl) / kLaneGroup;
   const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
   const uint64_t below = (1ull << lane) - 1;       // lanes under this one
   const uint64_t upto = below | (1ull << lane);    // lanes up to this one
   const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (blockDim.x / 64);
   gptr<uint32_t> slots = to_global(uniptr(static_cast<const uint32_t*>(hdr->slots)));
   const gout<uint64_t> out64 = to_global_mut(uniptr_mut(reinterpret_cast<uint64_t*>(out)));
-  for (uint64_t grp = uni64(static_cast<uint64_t>(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6));
-       grp < ngroups; grp += nwaves) {
+  for (uint64_t grp = uni64(static_cast<uint64_t>(blockIdx.x) * (blockDim.x / 64) + wv); grp < ngroups;
+       grp += nwaves) {
     const uint64_t l = grp * kLaneGroup + lane;
-    const uint64_t my_pos = hdr->lane_pos[l];
-    const uint64_t my_cnt = hdr->lane_cnt[l];
-    const uint64_t my_words = hdr->lane_words[l];
-    const uint64_t my_s0 = hdr->slot_off[l];
-    const uint64_t my_cap = hdr->slot_off[l + 1] - my_s0;
-    for (int j = 0; j < 64; ++j) {
-      const uint64_t pos = uni64(shfl_idx64(my_pos, j));
-      const uint64_t cnt = uni64(shfl_idx64(my_cnt, j));
-      const uint64_t words = uni64(shfl_idx64(my_words, j));
-      const uint64_t s0 = uni64(shfl_idx64(my_s0, j));
-      const uint64_t cap = uni64(shfl_idx64(my_cap, j));
-      if (cnt == 0 || words > cap || pos >= hi || pos + cnt <= lo) continue;
-      uint32_t carry_u = 0;
-      bool carry_mark = false;
-      uint64_t epos = pos;   // output position of the next edge
-      for (uint64_t w0 = 0; w0 < words; w0 += 256) {
-        uint32_t x[4];
+    const uint64_t pos = hdr->lane_pos[l];
+    const uint64_t cnt = hdr->lane_cnt[l];
+    const uint64_t words = hdr->lane_words[l];
+    const uint64_t s0 = hdr->slot_off[l];
+    const uint64_t cap = hdr->slot_off[l + 1] - s0;
+    const bool in = cnt > 0 && words <= cap && pos < hi && pos + cnt > lo;
+    const uint64_t wn = in ? words : 0, en = in ? cnt : 0;
+    const uint64_t wincl = wave_inclusive<uint64_t>(wn);
+    const uint64_t eincl = wave_inclusive<uint64_t>(en);
+    const uint64_t total = uni64(shfl_idx64(wincl, 63));
+    sh_wpre[wv][lane] = wincl - wn;
+    if (lane == 63) sh_wpre[wv][kLaneGroup] = total;
+    sh_src[wv][lane] = s0 - (wincl - wn);
+    sh_dst[wv][lane] = pos - (eincl - en);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t j = 0;            // this lane's unit (moves forward only)
+    uint32_t carry_u = 0;      // source id carried from the previous instruction
+    bool carry_mark = false;   // the previous instruction ended with a mark
+    uint64_t ebase = 0;        // stream edges before the current instruction
+    for (uint64_t t0 = 0; t0 < total; t0 += 64 * kCompactSteps) {
+      uint32_t x[kCompactSteps];
+      uint32_t uj[kCompactSteps];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const uint64_t idx = w0 + r * 64 + lane;
-          x[r] = (idx < words) ? slots[s0 + idx] : 0u;
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const bool valid = w0 + r * 64 + lane < words;
-          const bool mark = valid && x[r] == kSourceMark;
-          const uint64_t mmask = __ballot(mark);
-          const bool after_mark = (lane == 0) ? carry_mark : ((mmask >> (lane - 1)) & 1ull) != 0;
-          const bool is_u = valid && after_mark;
-          const bool edge = valid && !mark && !is_u;
-          const uint64_t umask = __ballot(is_u);
-          const uint64_t emask = __ballot(edge);
-          const uint64_t mine = umask & upto;
-          const uint32_t u_here = static_cast<uint32_t>(
-              __shfl(static_cast<int>(x[r]), mine ? 63 - __clzll(static_cast<long long>(mine)) : 0, 64));
-          const uint32_t u = mine ? u_here : carry_u;
-          const uint64_t e = epos + static_cast<uint64_t>(__popcll(emask & below));
-          if (edge && e >= lo && e < hi) out64[e - lo] = (static_cast<uint64_t>(x[r]) << 32) | u;
-          if (umask) {
-            const int top = 63 - __clzll(static_cast<long long>(umask));
-            carry_u = static_cast<uint32_t>(__shfl(static_cast<int>(x[r]), top, 64));
-          }
-          carry_mark = (mmask >> 63) != 0;
-          epos += static_cast<uint64_t>(__popcll(emask));
+      for (int r = 0; r < kCompactSteps; ++r) {
+        const uint64_t t = t0 + r * 64 + lane;
+        x[r] = 0u;
+        uj[r] = j;
+        if (t < total) {
+          while (t >= sh_wpre[wv][j + 1]) ++j;   // t < total, so j stays below 64
+          uj[r] = j;
+          x[r] = slots[sh_src[wv][j] + t];
         }
       }
+#pragma unroll
+      for (int r = 0; r < kCompactSteps; ++r) {
+        const bool valid = t0 + r * 64 + lane < total;
+        const bool mark = valid && x[r] == kSourceMark;
+        const uint64_t mmask = __ballot(mark);
+        const bool after_mark = (lane == 0) ? carry_mark : ((mmask >> (lane - 1)) & 1ull) != 0;
+        const bool is_u = valid && after_mark;
+        const bool edge = valid && !mark && !is_u;
+        const uint64_t umask = __ballot(is_u);
+        const uint64_t emask = __ballot(edge);
+        const uint64_t mine = umask & upto;
+        const uint32_t u_here = static_cast<uint32_t>(
+            __shfl(static_cast<int>(x[r]), mine ? 63 - __clzll(static_cast<long long>(mine)) : 0, 64));
+        const uint32_t u = mine ? u_here : carry_u;
+        if (edge) {
+          const uint64_t e = sh_dst[wv][uj[r]] + ebase + static_cast<uint64_t>(__popcll(emask & below));
+          if (e >= lo && e < hi) out64[e - lo] = (static_cast<uint64_t>(x[r]) << 32) | u;
+        }
+        if (umask) {
+          const int top = 63 - __clzll(static_cast<long long>(umask));
+          carry_u = static_cast<uint32_t>(__shfl(static_cast<int>(x[r]), top, 64));
+        }
+        carry_mark = (mmask >> 63) != 0;
+        ebase += static_cast<uint64_t>(__popcll(emask));
+      }
     }
+    __builtin_amdgcn_wave_barrier();   // the next group rewrites this wavefront's LDS
   }
 }
 

@@ -8,6 +8,14 @@ namespace cl {
 
 constexpr uint32_t kWsMagic = 0x434C5731u;  // "CLW1"
 constexpr uint32_t kCostUnit = 16;          // lane-plan cost units per expected candidate
+// Graded units: the last 1/kTailShare of a graph's plan cost is cut into units
+// kTailDiv times smaller than the lane budget, so that the lanes still busy
+// when the work queue runs dry finish soon after one another (a lane takes
+// about 0.5 ms for a unit of the default budget).  Graphs of fewer than
+// kTailMinUnits units keep uniform units.
+constexpr uint64_t kTailShare = 8;
+constexpr uint64_t kTailDiv = 4;
+constexpr uint64_t kTailMinUnits = 4096;
 constexpr uint32_t kLaneGroup = 64;         // lanes per work item (one wavefront)
 
 // status bits raised on the device
@@ -38,6 +46,7 @@ struct GraphDesc {
   uint64_t NH;       // heavy segments
   uint64_t hs_off;   // first heavy-table entry
   uint64_t L;        // lanes that carry work
+  uint64_t Lm, Zm;   // the first Lm units share the cost [0, Zm); the other L - Lm share [Zm, Z)
   uint64_t NL;       // lanes incl. padding to a multiple of 64
   uint64_t lane_off; // first lane
   uint64_t m;        // edges
@@ -45,6 +54,8 @@ struct GraphDesc {
   uint32_t status;
   uint32_t policy;   // host: 0 = units of equal cost, 1 = units of equal source counts,
                      // 2 = round robin (unit i takes segments i, i + L, i + 2L, ...)
+  uint32_t graded;   // host: policy 0 with smaller units for the last share of the cost
+  uint32_t pad;
 };
 
 struct Triple {

@@ -126,7 +126,8 @@ def test_source_ranges_bit_exact(planner, cg, u0, u1):
 @pytest.mark.parametrize("tuning", [{"lane_budget": 1}, {"lane_budget": 17}, {"lane_budget": 4096},
                                     {"lane_budget": 192, "blocks_per_cu": 1}, {"blocks_per_cu": 32},
                                     {"partition": 1}, {"partition": 1, "lane_budget": 1},
-                                    {"partition": 1, "lane_budget": 1 << 20}])
+                                    {"partition": 1, "lane_budget": 1 << 20}, {"tail_units": 1},
+                                    {"lane_budget": 17, "tail_units": 1}])
 @pytest.mark.parametrize("planner", PLANNERS)
 def test_schedule_does_not_change_output(planner, cg, tuning):
     w = _heavy(30000, 60, 40.0)
@@ -345,3 +346,19 @@ def test_sample_into_one_call(cg, tuning):
     edges.fill_(-1)
     plan3, fits3 = cg.cl_sample_into(tasks, edges, tuning=tuning, ws=plan.ws)
     assert fits3 and np.array_equal(_edges_np(edges)[:m], want)
+
+
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_graded_units_change_only_the_schedule(planner, cg):
+    """Graded units (the last eighth of the cost in units a quarter of the
+    lane budget) against uniform units on a graph of several thousand units:
+    more units, the same edges as the oracle."""
+    w = W.config_plain(n=300_000)
+    S = O.exact_sum(w)
+    want, m, _, _ = O.generate(w, S, 13)
+    lanes = {}
+    for tail in (0, 1):
+        got, plan = _gpu_edges(cg, w, S, 13, tuning={"tail_units": tail}, planner=planner)
+        assert np.array_equal(got, want), tail
+        lanes[tail] = cg.cl_plan_info(plan)["lanes"]
+    assert lanes[1] >= 4096 and lanes[0] > lanes[1]
