@@ -1156,7 +1156,7 @@ __global__ void k_slot_check(WsHeader* hdr) {
 // The unit of a word comes from the group's word prefix in LDS (a lane's
 // unit index only moves forward); edge k of the stream lies in unit j and
 // goes to position lane_pos[j] + (k - edges of the stream before unit j).
-constexpr int kCompactSteps = 4;
+constexpr int kCompactSteps = 8;
 
 __global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out, uint64_t lo, uint64_t hi) {
   __shared__ uint64_t sh_wpre[4][kLaneGroup + 1];   // stream position of each unit's first word, then the total
@@ -1191,22 +1191,30 @@ __global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    uint32_t j = 0;            // this lane's unit (moves forward only)
+    uint32_t j = 0;            // this lane's unit (moves forward only), and its fields
+    uint64_t j_end = sh_wpre[wv][1], j_src = sh_src[wv][0], j_dst = sh_dst[wv][0];
     uint32_t carry_u = 0;      // source id carried from the previous instruction
     bool carry_mark = false;   // the previous instruction ended with a mark
     uint64_t ebase = 0;        // stream edges before the current instruction
     for (uint64_t t0 = 0; t0 < total; t0 += 64 * kCompactSteps) {
       uint32_t x[kCompactSteps];
-      uint32_t uj[kCompactSteps];
+      uint64_t dst[kCompactSteps];
 #pragma unroll
       for (int r = 0; r < kCompactSteps; ++r) {
         const uint64_t t = t0 + r * 64 + lane;
         x[r] = 0u;
-        uj[r] = j;
+        dst[r] = 0;
         if (t < total) {
-          while (t >= sh_wpre[wv][j + 1]) ++j;   // t < total, so j stays below 64
-          uj[r] = j;
-          x[r] = slots[sh_src[wv][j] + t];
+          if (t >= j_end) {
+            do {
+              ++j;   // t < total, so j stays below 64
+            } while (t >= sh_wpre[wv][j + 1]);
+            j_end = sh_wpre[wv][j + 1];
+            j_src = sh_src[wv][j];
+            j_dst = sh_dst[wv][j];
+          }
+          dst[r] = j_dst;
+          x[r] = slots[j_src + t];
         }
       }
 #pragma unroll
@@ -1224,7 +1232,7 @@ __global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out
             __shfl(static_cast<int>(x[r]), mine ? 63 - __clzll(static_cast<long long>(mine)) : 0, 64));
         const uint32_t u = mine ? u_here : carry_u;
         if (edge) {
-          const uint64_t e = sh_dst[wv][uj[r]] + ebase + static_cast<uint64_t>(__popcll(emask & below));
+          const uint64_t e = dst[r] + ebase + static_cast<uint64_t>(__popcll(emask & below));
           if (e >= lo && e < hi) out64[e - lo] = (static_cast<uint64_t>(x[r]) << 32) | u;
         }
         if (umask) {
