@@ -19,6 +19,42 @@ namespace cl {
 // --------------------------------------------------------------------------
 // helpers
 // --------------------------------------------------------------------------
+// pointers into global memory (address space 1), so that loads through them
+// are global loads rather than generic ones
+template <class T>
+using gptr = const T __attribute__((address_space(1)))*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> to_global(const T* p) {
+  return (gptr<T>)(p);
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// writable global pointers (stores with immediate offsets, no LDS aperture check)
+template <class T>
+using gout = T __attribute__((address_space(1)))*;
+
+template <class T>
+__device__ __forceinline__ gout<T> to_global_mut(T* p) {
+  return (gout<T>)(p);
+}
+
+// wave-uniform copies of values that are equal on every lane (they then live
+// in scalar registers)
+__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+  return (static_cast<uint64_t>(uni32(static_cast<uint32_t>(x >> 32))) << 32) | uni32(static_cast<uint32_t>(x));
+}
+template <class T>
+__device__ __forceinline__ const T* uniptr(const T* p) {
+  return reinterpret_cast<const T*>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+template <class T>
+__device__ __forceinline__ T* uniptr_mut(T* p) {
+  return reinterpret_cast<T*>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+
 // largest g in [0, G) with off(g) <= i (offsets non-decreasing, off(0) = 0)
 template <class F>
 __device__ __forceinline__ uint32_t find_graph(uint32_t G, uint64_t i, F off) {
@@ -473,9 +509,9 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
   const GraphDesc* desc = hdr->desc;
   const uint32_t G = hdr->G;
   const uint64_t NH = hdr->total_nh;
-  const uint64_t* SB = hdr->SB;
-  const uint64_t* Q = hdr->Q;
-  HSeg* hseg = hdr->hseg;
+  const gptr<uint64_t> SB = to_global(hdr->SB);
+  const gptr<uint64_t> Q = to_global(hdr->Q);
+  const gout<u32x4> hseg = to_global_mut(reinterpret_cast<u32x4*>(hdr->hseg));   // HSeg {u, k, j, send}
   const HeavyCtx c0 = heavy_ctx(desc[0]);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t h = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; h < NH; h += stride) {
@@ -492,7 +528,7 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
     const uint64_t K = SB[c.r_off + r + 1] - sbr;
     const uint64_t k = hl - (sbr - c.SB0);
     const uint64_t u = c.u_begin + r;
-    const uint64_t* Qg = Q + c.q_off;
+    const gptr<uint64_t> Qg = Q + c.q_off;
     const uint64_t base = Qg[u + 1] - c.Qbase;
     const uint64_t Dm = c.Qn - base;
     // b_kk = first v in [u+1, n] with Q_v - Q_{u+1} >= kk floor(D/K) + floor(kk (D mod K) / K)
@@ -514,8 +550,8 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
         if (q1 >= t1) hi1 = m1; else lo1 = m1 + 1;
       }
     }
-    hseg[h] = HSeg{static_cast<uint32_t>(u), static_cast<uint32_t>(k), static_cast<uint32_t>(lo0),
-                   static_cast<uint32_t>(lo1)};
+    hseg[h] = u32x4{static_cast<uint32_t>(u), static_cast<uint32_t>(k), static_cast<uint32_t>(lo0),
+                    static_cast<uint32_t>(lo1)};
   }
 }
 
@@ -556,18 +592,18 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
   const GraphDesc* desc = hdr->desc;
   const uint32_t G = hdr->G;
   const uint64_t total_r = hdr->total_r;
-  const uint64_t* C = hdr->C;
-  const uint64_t* SB = hdr->SB;
-  double* A = hdr->A;
-  uint32_t* lane_seg = hdr->lane_seg;
-  uint64_t* lane_cum = hdr->lane_cum;
+  const gptr<uint64_t> C = to_global(hdr->C);
+  const gptr<uint64_t> SB = to_global(hdr->SB);
+  const gout<double> A = to_global_mut(hdr->A);
+  const gout<uint32_t> lane_seg = to_global_mut(hdr->lane_seg);
+  const gout<uint64_t> lane_cum = to_global_mut(hdr->lane_cum);
   const PlanCtx c0 = plan_ctx(desc[0]);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total_r; i += stride) {
     const PlanCtx d = (G == 1) ? c0 : plan_ctx(desc[find_graph(G, i, [&](uint32_t x) { return desc[x].r_off; })]);
     const uint64_t r = i - d.r_off;
     if (r >= d.nr) continue;
-    A[i] = d.w[d.u_begin + r] / d.S;  // a_u of Alg. 1, once per source
+    A[i] = to_global(d.w)[d.u_begin + r] / d.S;  // a_u of Alg. 1, once per source
     if (d.L == 0 || d.policy == 2) continue;   // round-robin starts are set with the groups
     const uint64_t L = d.L;
     const uint64_t cex = C[i] - d.C0;
@@ -633,42 +669,6 @@ __global__ void __launch_bounds__(256) k_lane_groups(const WsHeader* hdr) {
 // --------------------------------------------------------------------------
 // the per-lane Create-Edges loop
 // --------------------------------------------------------------------------
-// pointers into global memory (address space 1), so that loads through them
-// are global loads rather than generic ones
-template <class T>
-using gptr = const T __attribute__((address_space(1)))*;
-
-template <class T>
-__device__ __forceinline__ gptr<T> to_global(const T* p) {
-  return (gptr<T>)(p);
-}
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// writable global pointers (stores with immediate offsets, no LDS aperture check)
-template <class T>
-using gout = T __attribute__((address_space(1)))*;
-
-template <class T>
-__device__ __forceinline__ gout<T> to_global_mut(T* p) {
-  return (gout<T>)(p);
-}
-
-// wave-uniform copies of values that are equal on every lane (they then live
-// in scalar registers)
-__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ uint64_t uni64(uint64_t x) {
-  return (static_cast<uint64_t>(uni32(static_cast<uint32_t>(x >> 32))) << 32) | uni32(static_cast<uint32_t>(x));
-}
-template <class T>
-__device__ __forceinline__ const T* uniptr(const T* p) {
-  return reinterpret_cast<const T*>(uni64(reinterpret_cast<uint64_t>(p)));
-}
-template <class T>
-__device__ __forceinline__ T* uniptr_mut(T* p) {
-  return reinterpret_cast<T*>(uni64(reinterpret_cast<uint64_t>(p)));
-}
-
 struct LaneCtx {
   gptr<double> w;
   gptr<double> A;                 // a_u = w_u / S of the range's sources (index u - u_begin)
