@@ -115,8 +115,9 @@ def log(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single "
-              f"MI355X; see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the generator runs on a single "
+              f"MI355X (across GPUs, each would take parts of the uniform consecutive partition, Eq. 5)",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
