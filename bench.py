@@ -26,6 +26,8 @@ second.  Printed as one JSON line, with:
 * two_pass: the count-then-replay path (count pass, offsets, write pass);
 * expected_degree: the float32 tiled expected-degree kernel and its adjoint
   on n = 1e5 (1e10 pairs), against the VALU lane-operation peak;
+* csr: the same plan written as compressed sparse rows (4-byte targets and
+  row offsets) instead of (u, v) pairs;
 * calibration: 200 Adam steps on log w against n = 1e5 capped targets, then
   generation from the calibrated weights;
 * partition_ablation: generation-kernel time with work units of equal
@@ -93,6 +95,7 @@ def parse():
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-expdeg", action="store_true")
     ap.add_argument("--no-calib", action="store_true")
+    ap.add_argument("--no-csr", action="store_true")
     ap.add_argument("--full-graph-degrees", action="store_true",
                     help="instead of the step: the degree sequence of the whole n=1e9 graph (exponent 2.1, mean "
                          "degree 500), every edge generated and consumed on the fly, part by part")
@@ -248,6 +251,8 @@ def main():
     }
     if not args.no_two_pass:
         result["two_pass"] = bench_two_pass(args, cg, torch, w, seed, dev, stream)
+    if not args.no_csr:
+        result["csr"] = bench_csr(cg, torch, w, seed, plan, t_copy)
 
     if not args.no_ablation:
         result["partition_ablation"] = bench_partition(cg, torch, w, seed)
@@ -350,6 +355,27 @@ def bench_expdeg(cg, W, torch, dev, reps=5):
         out[f"{name}_pairs_per_s"] = n * n / (ms * 1e-3)
         out[f"{name}_alu_frac"] = n * n * ops / (ms * 1e-3) / PEAK_LANE_OPS
     return out
+
+
+def bench_csr(cg, torch, w, seed, plan, pairs_ms):
+    """The same one-pass plan written as compressed sparse rows
+    (cl_generate_csr: 4-byte targets plus row offsets) instead of (u, v)
+    pairs; timed with events around the call (which first reads the plan's
+    sizes back)."""
+    m = plan.total
+    col = torch.empty(m, dtype=torch.int32, device=w.device)
+    rows = torch.empty(w.numel() + 1, dtype=torch.int64, device=w.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(4):
+        e0.record()
+        cg.cl_generate_csr(plan, col=col, row_ptr=rows)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t = min(ms[1:])
+    return {"edges": m, "csr_ms": t, "pairs_expansion_ms": pairs_ms * 1e3,
+            "bytes_written": 4 * m + 8 * (w.numel() + 1), "GBps_written": (4 * m + 8 * (w.numel() + 1)) / t / 1e6}
 
 
 def bench_calibration(cg, W, torch, dev, steps=200):

@@ -190,6 +190,22 @@ cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t ed
                       uint64_t* graph_offsets, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The same edges as compressed sparse rows (the generator's output consumed
+ * on the fly, Sec. 5): col[pos] = v for the edge (u, v) at batch position pos
+ * (4 bytes per edge instead of 8), and row_ptr[q_g + u] = the batch position
+ * of the first edge of source u of task g, q_g = sum over earlier tasks h of
+ * (n_h + 1), so that the targets of u are col[row_ptr[q_g + u] ..
+ * row_ptr[q_g + u + 1]) and row_ptr[q_g + n_g] = off_g + m_g.  Rows of sources
+ * outside the task's range are empty.  col: device uint32, cap >= total m;
+ * row_ptr: device uint64, row_len >= sum_g (n_g + 1); else CL_ERR_CAPACITY.
+ * ws must hold the plan of a successful cl_count, cl_sample or
+ * cl_sample_into.  Synchronises once (reads the plan's sizes), then
+ * launches asynchronously.
+ * ------------------------------------------------------------------------- */
+cl_status cl_generate_csr(void* ws, const cl_tuning* t, uint32_t* col, uint64_t cap, uint64_t* row_ptr,
+                          uint64_t row_len, void* stream);
+
+/* ---------------------------------------------------------------------------
  * The plan alone (validation, quantised prefix, segments, lane plan), without
  * running the lanes: for cl_degrees, which needs no counts.  ws as for
  * cl_count (cl_workspace_size with one_pass = 0 bounds it).  cl_generate on

@@ -79,6 +79,7 @@ def lib():
                               ctypes.POINTER(ctypes.c_uint32), _U64P, _P]),
         "cl_hash_edges": (S, [_P, _U64, _U64, _P, _P]),
         "cl_degrees": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _P]),
+        "cl_generate_csr": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _P, _U64, _P]),
         "cl_plan": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _U64, _U64P,
                         _P]),
         "cl_batch_capture": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _P, _U64,
@@ -300,6 +301,31 @@ def cl_generate(plan: Plan, edges: Optional[torch.Tensor] = None, edge_begin: in
     _check(L.cl_generate(_ptr(plan.ws), _tuning(plan.tuning), _ptr(edges), int(edge_begin), int(cap),
                          _ptr(graph_offsets), _stream(stream)), "cl_generate")
     return edges[: int(cap)]
+
+
+def cl_generate_csr(plan: Plan, col: Optional[torch.Tensor] = None, row_ptr: Optional[torch.Tensor] = None,
+                    stream=None):
+    """The planned edges as compressed sparse rows: col (int32 tensor holding
+    uint32 targets, one per edge in batch order) and, per task, a view of
+    row_ptr (int64, n_g + 1 entries: the batch position of each source's
+    first edge, then the task's end).  Returns (col[:m], [row views])."""
+    L = lib()
+    sizes = [int(t.w.numel()) for t in plan.tasks]
+    total = sum(n + 1 for n in sizes)
+    m = plan.total
+    dev = plan.ws.device
+    if col is None:
+        col = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    if row_ptr is None:
+        row_ptr = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
+    assert col.dtype == torch.int32 and col.is_contiguous() and row_ptr.dtype == torch.int64
+    _check(L.cl_generate_csr(_ptr(plan.ws), _tuning(plan.tuning), _ptr(col), int(col.numel()), _ptr(row_ptr),
+                             int(row_ptr.numel()), _stream(stream)), "cl_generate_csr")
+    rows, off = [], 0
+    for n in sizes:
+        rows.append(row_ptr[off: off + n + 1])
+        off += n + 1
+    return col[:m], rows
 
 
 def cl_degrees(plan: Plan, deg: Optional[torch.Tensor] = None, stream=None) -> List[torch.Tensor]:

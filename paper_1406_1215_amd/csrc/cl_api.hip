@@ -25,6 +25,7 @@ constexpr uint64_t kAlign = 256;
 constexpr uint32_t kDefaultBudget = 192;
 constexpr uint32_t kDefaultBlocksPerCu = 3;
 constexpr int kPersistThreads = 256;
+unsigned long long* const kNoRows = nullptr;   // row counts: CSR output only
 static_assert(kPersistThreads == kLaneThreads, "the lane kernels stage output for 256 threads");
 
 inline uint64_t align_up(uint64_t x, uint64_t a = kAlign) { return (x + a - 1) / a * a; }
@@ -183,7 +184,7 @@ hipError_t launch_plan_front(WsHeader* dhdr, const WsHeader& h, uint32_t G, hipS
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(256), 0, s, dhdr);
   hipLaunchKernelGGL(k_graph_init, dim3((G + 255) / 256), dim3(256), 0, s, h.desc, G);
   hipLaunchKernelGGL((k_validate<false>), dim3(grid_for(h.total_q, 256, cap)), dim3(256), 0, s, h.desc, G,
-                     h.total_q, static_cast<unsigned long long*>(nullptr));
+                     h.total_q, kNoRows);
   hipError_t e = device_scan<uint64_t>(QIn{h.desc, G}, QOut{h.desc, G, h.Q}, h.total_q, h.scan_tmp, s);
   if (e != hipSuccess) return e;
   e = device_scan<Triple>(NodeIn{h.desc, G, h.Q}, NodeOut{h.desc, G, h.C, h.SB}, h.total_r,
@@ -215,12 +216,12 @@ hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* 
     hipLaunchKernelGGL(k_slot_check, dim3(1), dim3(1), 0, s, dhdr);
     if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL((k_lanes<2>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                       static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr));
+                       static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr), kNoRows);
     if (ev1) (void)hipEventRecord(ev1, s);
   } else {
     if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL((k_lanes<0>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                       static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr));
+                       static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr), kNoRows);
     if (ev1) (void)hipEventRecord(ev1, s);
   }
   hipError_t e = device_scan<uint64_t>(CntIn{{}, h.lane_cnt, h.cap_nl}, OffOut{{}, h.lane_pos}, h.cap_nl + 1,
@@ -237,10 +238,11 @@ hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* 
 hipError_t launch_write(WsHeader* dhdr, const cl_tuning* t, uint32_t* edges, uint64_t lo, uint64_t hi,
                         uint64_t* graph_offsets, hipStream_t s) {
   const uint32_t cus = std::max<uint32_t>(cus_of_current_device(), 1);
-  hipLaunchKernelGGL(k_compact, dim3(cus * 16), dim3(256), 0, s, dhdr, reinterpret_cast<uint2*>(edges), lo, hi);
+  hipLaunchKernelGGL((k_compact<false>), dim3(cus * 16), dim3(256), 0, s, dhdr, reinterpret_cast<uint2*>(edges), lo,
+                     hi, kNoRows);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
   hipLaunchKernelGGL((k_lanes<1>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                     reinterpret_cast<uint2*>(edges), lo, hi, static_cast<uint32_t*>(nullptr));
+                     reinterpret_cast<uint2*>(edges), lo, hi, static_cast<uint32_t*>(nullptr), kNoRows);
   if (graph_offsets) hipLaunchKernelGGL(k_graph_offsets, dim3(16), dim3(256), 0, s, dhdr, graph_offsets);
   return hipGetLastError();
 }
@@ -380,7 +382,7 @@ cl_status cl_partition(const double* w, uint64_t n, double S, uint32_t P, void* 
   const uint32_t cap = stream_grid_cap();
   hipLaunchKernelGGL(k_graph_init, dim3(1), dim3(64), 0, s, d, 1u);
   hipLaunchKernelGGL((k_validate<false>), dim3(grid_for(n + 1, 256, cap)), dim3(256), 0, s, d, 1u, n + 1,
-                     static_cast<unsigned long long*>(nullptr));
+                     kNoRows);
   CL_TRY((device_scan<uint64_t>(QIn{d, 1u}, QOut{d, 1u, Q}, n + 1, tmp, s)));
   CL_TRY((device_scan<uint64_t>(PartIn{{}, d, Q}, PartOut{{}, C}, n + 1, tmp, s)));
   hipLaunchKernelGGL(k_part_bounds, dim3(grid_for(static_cast<uint64_t>(P) + 1, 256, 1024)), dim3(256), 0, s, C, n,
@@ -626,8 +628,36 @@ cl_status cl_degrees(void* ws, const cl_tuning* t, uint32_t* deg, uint64_t deg_l
   if (deg_len < back.total_q) return CL_ERR_CAPACITY;
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
   hipLaunchKernelGGL((k_lanes<3>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                     static_cast<uint2*>(nullptr), 0ull, 0ull, deg);
+                     static_cast<uint2*>(nullptr), 0ull, 0ull, deg, kNoRows);
   return hip_status(hipGetLastError());
+}
+
+cl_status cl_generate_csr(void* ws, const cl_tuning* t, uint32_t* col, uint64_t cap, uint64_t* row_ptr,
+                          uint64_t row_len, void* stream) {
+  if (!ws || !row_ptr || (cap > 0 && !col)) return CL_ERR_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  WsHeader* dhdr = static_cast<WsHeader*>(ws);
+  WsHeader back{};
+  CL_TRY(hipMemcpyAsync(&back, ws, sizeof(back), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipStreamSynchronize(s));
+  if (back.magic != kWsMagic) return CL_ERR_NOT_PLANNED;
+  if (back.status) return status_error(back.status);
+  if (back.planned != 1) return CL_ERR_NOT_PLANNED;
+  if (row_len < back.total_q || cap < back.total_m) return CL_ERR_CAPACITY;
+  unsigned long long* rows = reinterpret_cast<unsigned long long*>(row_ptr);
+  const uint32_t cus = std::max<uint32_t>(cus_of_current_device(), 1);
+  hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(back.total_q, 256, stream_grid_cap())), dim3(256), 0, s, rows,
+                     back.total_q);
+  // one-pass plans: the slots; then the replay of overflowed units (one-pass
+  // plans) or of every unit (two-pass plans); then the row offsets
+  hipLaunchKernelGGL((k_compact<true>), dim3(cus * 16), dim3(256), 0, s, dhdr, reinterpret_cast<uint2*>(col), 0ull,
+                     cap, rows);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
+  hipLaunchKernelGGL((k_lanes<4>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
+                     reinterpret_cast<uint2*>(col), 0ull, cap, static_cast<uint32_t*>(nullptr), rows);
+  CL_TRY(hipGetLastError());
+  CL_TRY(device_scan<uint64_t>(RowIn{{}, rows, back.total_q}, RowOut{{}, rows}, back.total_q, back.scan_tmp, s));
+  return CL_OK;
 }
 
 cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments, uint64_t* edges,

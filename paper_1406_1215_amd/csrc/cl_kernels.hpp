@@ -893,6 +893,58 @@ struct WordEmit {
   }
 };
 
+// CSR write pass: every kept edge (u, v) writes v at its batch position of
+// the column array (staged in 64-byte chunks of 16 words like WordEmit, the
+// chunks aligned to position 0) and counts one edge for row u; the count of
+// a run of equal u is kept in a register and added to rows[u] once.
+struct CsrEmit {
+  uint32_t* stage;                // LDS, kWordSlots x kLaneThreads words
+  gout<uint32_t> col;             // column array: col[i] is batch position i
+  unsigned long long* rows;       // per-source edge counts of the bound graph
+  uint64_t pos, hi;               // next position, end of the unit's range
+  uint32_t run;                   // words staged by this unit (saturates at kWordSlots)
+  uint32_t cur, cnt;              // source of the current run and its edges so far
+  __device__ uint32_t& slot(uint64_t q) { return stage[(q & (kWordSlots - 1)) * kLaneThreads + threadIdx.x]; }
+  __device__ void store(uint64_t qend, uint32_t own) {
+    const uint64_t q0 = (qend - 1) & ~static_cast<uint64_t>(kWordSlots - 1);
+    if (own == kWordSlots) {
+      gout<u32x4> dst = reinterpret_cast<gout<u32x4>>(col + q0);
+#pragma unroll
+      for (int i = 0; i < kWordSlots / 4; ++i)
+        dst[i] = u32x4{stage[(4 * i) * kLaneThreads + threadIdx.x], stage[(4 * i + 1) * kLaneThreads + threadIdx.x],
+                       stage[(4 * i + 2) * kLaneThreads + threadIdx.x], stage[(4 * i + 3) * kLaneThreads + threadIdx.x]};
+    } else {
+      for (uint64_t q = qend - own; q < qend; ++q) col[q] = slot(q);
+    }
+  }
+  __device__ void count_flush() {
+    if (cnt) atomicAdd(&rows[cur], static_cast<unsigned long long>(cnt));
+    cnt = 0;
+  }
+  __device__ bool operator()(uint32_t u, uint32_t v) {
+    if (pos >= hi) return false;
+    if (u != cur) {
+      count_flush();
+      cur = u;
+    }
+    ++cnt;
+    slot(pos) = v;
+    if (run < kWordSlots) ++run;
+    if ((pos & (kWordSlots - 1)) == kWordSlots - 1) {
+      store(pos + 1, run);
+      run = kWordSlots;
+    }
+    ++pos;
+    return true;
+  }
+  // the unit's last, incomplete chunk and its last run
+  __device__ void finish() {
+    const uint32_t part = static_cast<uint32_t>(pos & (kWordSlots - 1));
+    if (part) store(pos, (run < part) ? run : part);
+    count_flush();
+  }
+};
+
 // Degree consumer: every kept edge (u, v) adds 1 to the degrees of u and v,
 // and no edge is stored.  The source's count is kept in a register and added
 // once per run of equal u; integer additions commute, so the result does not
@@ -933,6 +985,10 @@ template <>
 struct EmitOf<1> {
   using type = WriteEmit;
 };
+template <>
+struct EmitOf<4> {
+  using type = CsrEmit;
+};
 
 // The lane kernel.  kMode 0: count pass.  kMode 1: write pass (replay into
 // the output window; in one-pass plans only the units that overflowed their
@@ -948,15 +1004,16 @@ struct EmitOf<1> {
 // registers); a chunk of another graph is handed out once every lane is idle.
 template <int kMode>
 __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* out, uint64_t e_lo, uint64_t e_hi,
-                                                       uint32_t* deg) {
+                                                       uint32_t* deg, unsigned long long* rows) {
   using Emit = typename EmitOf<kMode>::type;
-  constexpr bool kWrite = (kMode == 1 || kMode == 2);
+  constexpr bool kWrite = (kMode == 1 || kMode == 2 || kMode == 4);
+  constexpr bool kReplay = (kMode == 1 || kMode == 4);
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   __shared__ uint2 stage[kWrite ? kStageSlots * kLaneThreads : 1];
   if (hdr->status || hdr->magic != kWsMagic) return;
-  if (kMode == 1 && hdr->planned != 1) return;   // the write pass needs the counts
+  if (kReplay && hdr->planned != 1) return;   // the write passes need the counts
   if (kMode == 3 && !hdr->planned) return;
-  const bool only_overflow = (kMode == 1) && (uni32(hdr->mode) == 1);
+  const bool only_overflow = kReplay && (uni32(hdr->mode) == 1);
   if (only_overflow && uni32(hdr->overflow) == 0) return;
   const GraphDesc* desc = hdr->desc;
   const uint32_t ngroups = uni32(static_cast<uint32_t>(uni64(hdr->total_nl) / kLaneGroup));
@@ -981,6 +1038,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
   uint32_t nseg = 0;         // segments of the graph
   bool rr = false;           // round-robin units
   uint32_t* degp = nullptr;  // degree mode: the graph's degree array
+  unsigned long long* rowp = nullptr;   // CSR mode: the graph's row counts
   uint32_t cnext = 0, cend = 0, cgraph = kNone;
   bool queue_done = false;
 
@@ -1046,6 +1104,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
           unit_end = uni64(d.lane_off) + uni64(d.NL);
           nseg = uni32(static_cast<uint32_t>(d.SB1 - d.SB0));
           if constexpr (kMode == 3) degp = uniptr_mut(deg) + uni64(d.q_off);
+          if constexpr (kMode == 4) rowp = uniptr_mut(rows) + uni64(d.q_off);
         }
         // rank of this lane among the idle lanes
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(idle_mask >> 32),
@@ -1070,7 +1129,11 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
             touched = (pos0 < e_hi) && (pos0 + cnt > e_lo);
             // one-pass plans: only the units whose words did not fit their slot
             if (only_overflow) touched = touched && (lane_words[unit] > slot_off[unit + 1] - slot_off[unit]);
-            em = WriteEmit{stage, outw, e_lo, pos0, e_hi, 0u};
+            if constexpr (kMode == 4)
+              em = CsrEmit{reinterpret_cast<uint32_t*>(stage), to_global_mut(reinterpret_cast<uint32_t*>(out)), rowp,
+                           pos0, e_hi, 0u, kNone, 0u};
+            else
+              em = WriteEmit{stage, outw, e_lo, pos0, e_hi, 0u};
             if (!touched) s.sg_end = s.sg;
           }
         }
@@ -1158,7 +1221,14 @@ __global__ void k_slot_check(WsHeader* hdr) {
 // goes to position lane_pos[j] + (k - edges of the stream before unit j).
 constexpr int kCompactSteps = 8;
 
-__global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out, uint64_t lo, uint64_t hi) {
+//
+// With kCsr the output is the column array of the compressed sparse rows
+// form: v alone at the edge's position (4 bytes), and each run of edges of one
+// source inside an instruction adds its length to rows[q_g + u] (the first
+// lane of the run does, a run being a stretch of consecutive edge lanes).
+template <bool kCsr>
+__global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out, uint64_t lo, uint64_t hi,
+                                                 unsigned long long* rows) {
   __shared__ uint64_t sh_wpre[4][kLaneGroup + 1];   // stream position of each unit's first word, then the total
   __shared__ uint64_t sh_src[4][kLaneGroup];        // slot index of stream word t of unit j: sh_src[j] + t
   __shared__ uint64_t sh_dst[4][kLaneGroup];        // output position of stream edge k of unit j: sh_dst[j] + k
@@ -1171,8 +1241,11 @@ __global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out
   const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (blockDim.x / 64);
   gptr<uint32_t> slots = to_global(uniptr(static_cast<const uint32_t*>(hdr->slots)));
   const gout<uint64_t> out64 = to_global_mut(uniptr_mut(reinterpret_cast<uint64_t*>(out)));
+  const gout<uint32_t> out32 = to_global_mut(uniptr_mut(reinterpret_cast<uint32_t*>(out)));
   for (uint64_t grp = uni64(static_cast<uint64_t>(blockIdx.x) * (blockDim.x / 64) + wv); grp < ngroups;
        grp += nwaves) {
+    unsigned long long* rowp = nullptr;   // CSR: the group's graph's row counts
+    if constexpr (kCsr) rowp = uniptr_mut(rows) + uni64(hdr->desc[uni32(hdr->group_graph[grp])].q_off);
     const uint64_t l = grp * kLaneGroup + lane;
     const uint64_t pos = hdr->lane_pos[l];
     const uint64_t cnt = hdr->lane_cnt[l];
@@ -1233,7 +1306,16 @@ __global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out
         const uint32_t u = mine ? u_here : carry_u;
         if (edge) {
           const uint64_t e = dst[r] + ebase + static_cast<uint64_t>(__popcll(emask & below));
-          if (e >= lo && e < hi) out64[e - lo] = (static_cast<uint64_t>(x[r]) << 32) | u;
+          if constexpr (kCsr) {
+            if (e >= lo && e < hi) out32[e - lo] = x[r];
+            if (lane == 0 || ((emask >> (lane - 1)) & 1ull) == 0) {   // first lane of a run
+              const uint64_t rest = emask >> lane;
+              const uint32_t len = (rest == ~0ull) ? 64u : static_cast<uint32_t>(__builtin_ctzll(~rest));
+              atomicAdd(&rowp[u], static_cast<unsigned long long>(len));
+            }
+          } else {
+            if (e >= lo && e < hi) out64[e - lo] = (static_cast<uint64_t>(x[r]) << 32) | u;
+          }
         }
         if (umask) {
           const int top = 63 - __clzll(static_cast<long long>(umask));
@@ -1259,6 +1341,19 @@ struct CntIn : OneGraph {
 struct OffOut : OneGraph {
   uint64_t* off;
   __device__ void store(uint64_t i, Ctx, uint64_t, uint64_t ex) const { off[i] = ex; }
+};
+
+// CSR rows: per-source edge counts in, exclusive prefix (row offsets) out,
+// in place (every element is read before the same thread writes it)
+struct RowIn : OneGraph {
+  const unsigned long long* c;
+  uint64_t n;
+  __device__ uint64_t load(uint64_t i, Ctx) const { return (i < n) ? c[i] : 0; }
+};
+
+struct RowOut : OneGraph {
+  unsigned long long* r;
+  __device__ void store(uint64_t i, Ctx, uint64_t, uint64_t ex) const { r[i] = ex; }
 };
 
 __global__ void __launch_bounds__(256) k_graph_edges(WsHeader* hdr, uint64_t* m_dev) {

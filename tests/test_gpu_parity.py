@@ -362,3 +362,44 @@ def test_graded_units_change_only_the_schedule(planner, cg):
         assert np.array_equal(got, want), tail
         lanes[tail] = cg.cl_plan_info(plan)["lanes"]
     assert lanes[1] >= 4096 and lanes[0] > lanes[1]
+
+
+def _csr_of(edges, n, base=0):
+    """Row offsets and columns of a (u, v)-sorted edge list."""
+    u = edges[:, 0].astype(np.int64)
+    rows = np.concatenate([[0], np.cumsum(np.bincount(u, minlength=n))]) + base
+    return rows, edges[:, 1]
+
+
+@pytest.mark.parametrize("planner,tuning", [("cl_sample", None), ("cl_count", None),
+                                            ("cl_sample", {"slot_margin": 1}), ("cl_sample", {"tail_units": 1})])
+def test_csr_output(cg, planner, tuning):
+    """cl_generate_csr: targets at the edges' positions and row offsets per
+    source, against the oracle's edge list, for a batch of uneven graphs (a
+    source range included), from one-pass plans (with and without slot
+    overflow) and two-pass plans."""
+    ws_ = [W.config_plain(n=200_000), _heavy(20000, 95, 30.0), np.zeros(5), W.config_small()]
+    tasks, wants, ranges = [], [], [(0, None), (0, None), (0, None), (1000, 7000)]
+    for i, w in enumerate(ws_):
+        S = O.exact_sum(w) if O.exact_sum(w) > 0 else 1.0
+        u0, u1 = ranges[i]
+        wants.append(O.generate(w, S, 500 + i, u0, u1)[0])
+        tasks.append(cg.Task(_to_dev(w), S, 500 + i, u0, u1))
+    plan = getattr(cg, planner)(tasks, tuning=tuning)
+    assert plan.m == [x.shape[0] for x in wants]
+    col, rows = cg.cl_generate_csr(plan)
+    col = col.cpu().numpy().view(np.uint32)
+    off = 0
+    for i, (w, want) in enumerate(zip(ws_, wants)):
+        r_want, c_want = _csr_of(want, w.size, off)
+        assert np.array_equal(rows[i].cpu().numpy(), r_want), i
+        assert np.array_equal(col[off: off + want.shape[0]], c_want), i
+        off += want.shape[0]
+    # too small a column array
+    with pytest.raises(cg.ClError):
+        cg.cl_generate_csr(plan, col=torch_empty_i32(plan.total - 1))
+
+
+def torch_empty_i32(n):
+    import torch
+    return torch.empty(max(n, 1), dtype=torch.int32, device="cuda:0")
