@@ -83,7 +83,8 @@ typedef struct cl_tuning {
   uint32_t tail_units;     /* with partition 0: 0 = graded (default): the last 1/8 of a graph's
                               cost is cut into units 4 times smaller than lane_budget, so that the
                               lanes still busy when the work runs out finish close together
-                              (graphs of at least 4096 units); 1 = uniform units */
+                              (graphs of at least 4096 units; in a batch only the last task, since
+                              the queue hands out the tasks' units in order); 1 = uniform units */
 } cl_tuning;
 
 /* ---------------------------------------------------------------------------

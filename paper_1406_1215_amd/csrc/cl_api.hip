@@ -464,7 +464,9 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
     d.r_off = ro;
     d.budget = bu;
     d.policy = policy;
-    d.graded = (t && t->tail_units == 1) ? 0u : 1u;
+    // graded units only for the last task: the work queue hands out the units
+    // of the tasks in order, so only the last one's end leaves lanes idle
+    d.graded = ((t && t->tail_units == 1) || i + 1 != G) ? 0u : 1u;
     qo += g[i].n + 1;
     ro += (g[i].u_end - g[i].u_begin) + 1;
     desc[i] = d;
