@@ -199,12 +199,8 @@ constexpr int kLimbs = 36;
 
 __global__ void __launch_bounds__(64) k_sum_finalize(const unsigned long long* bins, double* S_out,
                                                      uint32_t* status) {
-  __shared__ unsigned long long sb[2 * kBins];
   if (blockIdx.x != 0) return;
   const int L = threadIdx.x;   // limb
-  // all bins into LDS first: the loads are independent, so they overlap
-  for (int i = L; i < 2 * kBins; i += 64) sb[i] = bins[i];
-  __syncthreads();
   uint64_t acc = 0, carry = 0;  // limb value acc + carry 2^64
   auto add_at = [&](uint64_t val, int sh) {
     const int li = sh >> 6;
@@ -216,7 +212,7 @@ __global__ void __launch_bounds__(64) k_sum_finalize(const unsigned long long* b
     carry += (acc < part) ? 1 : 0;
   };
   for (int b0 = 0; b0 < 2 * kBins; b0 += 64) {
-    const uint64_t mine = sb[b0 + L];
+    const uint64_t mine = bins[b0 + L];
     uint64_t nz = __ballot(mine != 0);
     while (nz) {
       const int k = __ffsll(static_cast<long long>(nz)) - 1;
