@@ -88,7 +88,7 @@ FixedLayout fixed_layout(const cl_graph* g, uint32_t G) {
   L.total_q = tq;
   L.total_r = tr;
   // scan partials: Triple tiles of the source scan or u64 tiles of the Q scan
-  L.scan_elems = std::max<uint64_t>(scan_tiles(tq), 3 * scan_tiles(tr)) + 8;
+  L.scan_elems = std::max<uint64_t>(scan_tiles(tq), 3 * scan_tiles<Triple>(tr)) + 8;
   uint64_t off = align_up(sizeof(WsHeader));
   L.off_desc = off;
   off = align_up(off + sizeof(GraphDesc) * G);

@@ -457,6 +457,8 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
       d.L = L;
       d.Lm = Lm;
       d.Zm = Zm;
+      d.um = (Zm > 0) ? static_cast<double>(Lm) / static_cast<double>(Zm) : 0.0;
+      d.ut = (Z > Zm) ? static_cast<double>(L - Lm) / static_cast<double>(Z - Zm) : 0.0;
       d.NH = nh;
       sg = nseg;
       cost = (L > 0) ? Z : 0;
@@ -491,10 +493,59 @@ __global__ void __launch_bounds__(256) k_plan_sizes(WsHeader* hdr) {
 }
 
 // --------------------------------------------------------------------------
-// heavy-segment table (one thread per heavy segment).  The graph's fields
-// are read once per thread into registers (before any store), and the two
-// boundary searches of a segment advance in lockstep so that their loads
-// overlap.
+// lane plan.  Lane i of a graph starts at the first segment whose
+// inclusive cumulative cost reaches T_i (Eq. 5 with P = L lanes), where a
+// segment of source u carries cost c_u / K_u; T_i = i Zm / Lm for i <= Lm and
+// Zm + (i - Lm) (Z - Zm) / (L - Lm) after (uniform units when Lm = L).
+// A segment with cost share (b, b'] holds the starts of the units i with
+// b < T_i <= b' (the graph's first segment also holds unit 0).  The plan
+// only schedules: the rates Lm / Zm, ... are rounded once per graph and
+// multiplied here.  The count of unit starts up to x is monotone in x and
+// neighbouring segments compute their common bound identically, so every
+// unit is claimed by exactly one segment and the lane starts stay in order.
+// The starts inside heavy sources are claimed by the heavy-segment table
+// (one thread per segment, so a source with many units is spread over
+// threads); those of the one-segment sources by the lane-plan kernel.
+// --------------------------------------------------------------------------
+struct PlanCtx {
+  const double* w;
+  double S;
+  uint64_t r_off, nr, u_begin, L, C0, SB0, lane_off, Lm, Zm, H, NH;
+  double um, ut;
+  uint32_t policy;
+  // the last unit whose start is at most x, as an integral double
+  __device__ double unit_at(double x) const {
+    const double zm = static_cast<double>(Zm);
+    if (x < zm || Lm == L) return floor(x * um);
+    return static_cast<double>(Lm) + floor((x - zm) * ut);
+  }
+  // units of equal cost whose starts are claimed here
+  __device__ bool equal_cost_units() const { return L != 0 && policy == 0; }
+};
+
+__device__ __forceinline__ PlanCtx plan_ctx(const GraphDesc& d) {
+  return PlanCtx{d.w,  d.S,  d.r_off, d.u_end - d.u_begin, d.u_begin, d.L, d.C0, d.SB0, d.lane_off, d.Lm, d.Zm,
+                 d.H,  d.NH, d.um,    d.ut,                d.policy};
+}
+
+// Units (flo, min(fhi, L - 1)] start at graph-relative segment seg, with plan
+// cost cum before it.
+__device__ __forceinline__ void claim_units(const PlanCtx& p, double flo, double fhi, uint64_t seg, uint64_t cum,
+                                            gout<uint32_t> lane_seg, gout<uint64_t> lane_cum) {
+  fhi = fmin(fhi, static_cast<double>(p.L - 1));
+  if (!(flo < fhi)) return;
+  const uint64_t ihi = static_cast<uint64_t>(fhi);
+  for (uint64_t li = static_cast<uint64_t>(flo + 1.0); li <= ihi; ++li) {
+    lane_seg[p.lane_off + li] = static_cast<uint32_t>(seg);
+    if (lane_cum) lane_cum[p.lane_off + li] = cum;
+  }
+}
+
+// --------------------------------------------------------------------------
+// heavy-segment table (one thread per heavy segment), and the unit starts
+// inside heavy segments.  The graph's fields are read once per thread into
+// registers (before any store), and the two boundary searches of a segment
+// advance in lockstep so that their loads overlap.
 // --------------------------------------------------------------------------
 struct HeavyCtx {
   uint64_t hs_off, H, r_off, SB0, u_begin, q_off, Qbase, Qn, n;
@@ -512,10 +563,15 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
   const gptr<uint64_t> SB = to_global(hdr->SB);
   const gptr<uint64_t> Q = to_global(hdr->Q);
   const gout<u32x4> hseg = to_global_mut(reinterpret_cast<u32x4*>(hdr->hseg));   // HSeg {u, k, j, send}
+  const gptr<uint64_t> C = to_global(hdr->C);
+  const gout<uint32_t> lane_seg = to_global_mut(hdr->lane_seg);
+  const gout<uint64_t> lane_cum = to_global_mut(hdr->lane_cum);
   const HeavyCtx c0 = heavy_ctx(desc[0]);
+  const PlanCtx p0 = plan_ctx(desc[0]);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t h = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; h < NH; h += stride) {
-    const HeavyCtx c = (G == 1) ? c0 : heavy_ctx(desc[find_graph(G, h, [&](uint32_t x) { return desc[x].hs_off; })]);
+    const uint32_t g = (G == 1) ? 0u : find_graph(G, h, [&](uint32_t x) { return desc[x].hs_off; });
+    const HeavyCtx c = (G == 1) ? c0 : heavy_ctx(desc[g]);
     const uint64_t hl = h - c.hs_off;
     // heavy source: last r in [0, H) with SB(r) - SB0 <= hl
     uint64_t lo = 0, hi = c.H;
@@ -526,6 +582,7 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
     const uint64_t r = lo;
     const uint64_t sbr = SB[c.r_off + r];
     const uint64_t K = SB[c.r_off + r + 1] - sbr;
+    const uint64_t cex = C[c.r_off + r], cin = C[c.r_off + r + 1];   // used after the searches
     const uint64_t k = hl - (sbr - c.SB0);
     const uint64_t u = c.u_begin + r;
     const gptr<uint64_t> Qg = Q + c.q_off;
@@ -552,45 +609,32 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
     }
     hseg[h] = u32x4{static_cast<uint32_t>(u), static_cast<uint32_t>(k), static_cast<uint32_t>(lo0),
                     static_cast<uint32_t>(lo1)};
+    const PlanCtx p = (G == 1) ? p0 : plan_ctx(desc[g]);
+    if (p.equal_cost_units()) {
+      // segment k's share (b_k, b_k+1] of the source's cost (C_u, C_u+1]
+      const double ce = static_cast<double>(cex - p.C0), ci = static_cast<double>(cin - p.C0);
+      const double per_seg = (ci - ce) / static_cast<double>(K);
+      auto bound = [&](uint64_t kk) {
+        return (kk == 0) ? ce : (kk == K) ? ci : ce + static_cast<double>(kk) * per_seg;
+      };
+      const double b0 = bound(k);
+      const double flo = (r == 0 && k == 0) ? -1.0 : p.unit_at(b0);
+      const uint64_t cum = static_cast<uint64_t>(b0);
+      claim_units(p, flo, p.unit_at(bound(k + 1)), hl, cum < cin - p.C0 ? cum : cin - p.C0, lane_seg, lane_cum);
+    }
   }
 }
 
-// --------------------------------------------------------------------------
-// lane plan.  Lane i of a graph starts at the first segment whose
-// inclusive cumulative cost reaches T_i (Eq. 5 with P = L lanes), where a
-// segment of source u carries cost c_u / K_u; T_i = i Zm / Lm for i <= Lm and
-// Zm + (i - Lm) (Z - Zm) / (L - Lm) after (uniform units when Lm = L).
-// --------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t lane_floor(uint64_t C, uint64_t L, uint64_t Z) {
-  return static_cast<uint64_t>(floor(static_cast<double>(C) * static_cast<double>(L) / static_cast<double>(Z)));
-}
+// Each thread takes kPlanUnroll sources per step, their loads (weight and
+// cost prefixes) issued together before any of them is used.  A single
+// graph has its own instance (kOne) with no per-source descriptor loads,
+// whose waits would also wait for the stores in flight.
+constexpr int kPlanUnroll = 4;
 
-struct PlanCtx {
-  const double* w;
-  double S;
-  uint64_t r_off, nr, u_begin, L, Z, C0, SB0, lane_off, Lm, Zm;
-  uint32_t policy;
-  // the last unit whose start T_i is at most C (monotone in C)
-  __device__ uint64_t unit_of(uint64_t C) const {
-    if (C < Zm || Lm == L) return lane_floor(C, Lm, Zm);
-    return Lm + lane_floor(C - Zm, L - Lm, Z - Zm);
-  }
-  __device__ double start_of(uint64_t i) const {
-    if (i <= Lm) return static_cast<double>(i) * static_cast<double>(Zm) / static_cast<double>(Lm);
-    return static_cast<double>(Zm) +
-           static_cast<double>(i - Lm) * static_cast<double>(Z - Zm) / static_cast<double>(L - Lm);
-  }
-};
-
-__device__ __forceinline__ PlanCtx plan_ctx(const GraphDesc& d) {
-  return PlanCtx{d.w,  d.S,         d.r_off, d.u_end - d.u_begin, d.u_begin, d.L, d.C1 - d.C0, d.C0, d.SB0,
-                 d.lane_off, d.Lm, d.Zm, d.policy};
-}
-
-__global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
-  if (hdr->status) return;
+template <bool kOne>
+__device__ __forceinline__ void lane_plan_sources(const WsHeader* hdr) {
   const GraphDesc* desc = hdr->desc;
-  const uint32_t G = hdr->G;
+  const uint32_t G = kOne ? 1u : hdr->G;
   const uint64_t total_r = hdr->total_r;
   const gptr<uint64_t> C = to_global(hdr->C);
   const gptr<uint64_t> SB = to_global(hdr->SB);
@@ -599,47 +643,68 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
   const gout<uint64_t> lane_cum = to_global_mut(hdr->lane_cum);
   const PlanCtx c0 = plan_ctx(desc[0]);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total_r; i += stride) {
-    const PlanCtx d = (G == 1) ? c0 : plan_ctx(desc[find_graph(G, i, [&](uint32_t x) { return desc[x].r_off; })]);
-    const uint64_t r = i - d.r_off;
-    if (r >= d.nr) continue;
-    A[i] = to_global(d.w)[d.u_begin + r] / d.S;  // a_u of Alg. 1, once per source
-    if (d.L == 0 || d.policy == 2) continue;   // round-robin starts are set with the groups
-    const uint64_t L = d.L;
-    const uint64_t cex = C[i] - d.C0;
-    if (d.policy == 1) {
-      // equal source counts: unit li starts at source floor(li nr / L), segment 0
-      // (L <= nr, so a source starts at most one unit)
-      const uint64_t li = (r * L + d.nr - 1) / d.nr;          // ceil(r L / nr)
-      if (li < L && (li * d.nr) / L == r) {
-        lane_seg[d.lane_off + li] = static_cast<uint32_t>(SB[i] - d.SB0);
-        if (lane_cum) lane_cum[d.lane_off + li] = cex;
-      }
-      continue;
+  for (uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i0 < total_r;
+       i0 += kPlanUnroll * stride) {
+    uint32_t gq[kPlanUnroll];
+    bool live[kPlanUnroll];
+    double wu[kPlanUnroll];
+    uint64_t cl[kPlanUnroll], ch[kPlanUnroll];
+#pragma unroll
+    for (int q = 0; q < kPlanUnroll; ++q) {
+      const uint64_t i = i0 + q * stride;
+      gq[q] = (G == 1) ? 0u : find_graph(G, i < total_r ? i : 0, [&](uint32_t x) { return desc[x].r_off; });
+      const PlanCtx d = (G == 1) ? c0 : plan_ctx(desc[gq[q]]);
+      const uint64_t r = i - d.r_off;
+      live[q] = (i < total_r) && (r < d.nr);   // r < nr: C[i + 1] is the graph's own
+      wu[q] = live[q] ? to_global(d.w)[d.u_begin + r] : 0.0;
+      cl[q] = live[q] ? C[i] : 0;
+      ch[q] = live[q] ? C[i + 1] : 0;
     }
-    const uint64_t cin = C[i + 1] - d.C0;
-    uint64_t ilo = (r == 0) ? 0 : d.unit_of(cex) + 1;
-    uint64_t ihi = d.unit_of(cin);
-    if (ihi > L - 1) ihi = L - 1;
-    if (ilo > ihi) continue;   // no unit starts at this source (most sources)
-    const uint64_t sbi = SB[i];
-    const uint64_t K = SB[i + 1] - sbi;
-    const double cnode = static_cast<double>(cin - cex);
-    for (uint64_t li = ilo; li <= ihi; ++li) {
-      const double Ti = d.start_of(li);
-      double kk = ceil((Ti - static_cast<double>(cex)) * static_cast<double>(K) / cnode) - 1.0;
-      if (!(kk > 0.0)) kk = 0.0;
-      if (kk > static_cast<double>(K - 1)) kk = static_cast<double>(K - 1);
-      lane_seg[d.lane_off + li] = static_cast<uint32_t>(sbi - d.SB0 + static_cast<uint64_t>(kk));
-      if (lane_cum) {
-        // plan cost before the lane's first segment (segments of a source share its cost equally)
-        const double before = static_cast<double>(cex) + kk * cnode / static_cast<double>(K);
-        uint64_t cb = static_cast<uint64_t>(before);
-        if (cb > cin) cb = cin;
-        lane_cum[d.lane_off + li] = cb;
+    // the unit starts of the one-segment sources (graph-relative segment
+    // NH + r - H), computed before any store: a wait for a load also waits
+    // for the stores issued before it
+    double flo[kPlanUnroll], fhi[kPlanUnroll];
+    uint64_t seg[kPlanUnroll];
+#pragma unroll
+    for (int q = 0; q < kPlanUnroll; ++q) {
+      flo[q] = 0.0;
+      fhi[q] = 0.0;
+      seg[q] = 0;
+      if (!live[q]) continue;
+      const uint64_t i = i0 + q * stride;
+      const PlanCtx d = (G == 1) ? c0 : plan_ctx(desc[gq[q]]);
+      const uint64_t r = i - d.r_off;
+      if (d.equal_cost_units()) {
+        if (r < d.H) continue;   // claimed segment by segment with the heavy table
+        flo[q] = (r == 0) ? -1.0 : d.unit_at(static_cast<double>(cl[q] - d.C0));
+        fhi[q] = d.unit_at(static_cast<double>(ch[q] - d.C0));
+        seg[q] = d.NH + (r - d.H);
+      } else if (d.L != 0 && d.policy == 1) {
+        // equal source counts: unit li starts at source floor(li nr / L), segment 0
+        // (L <= nr, so a source starts at most one unit); round-robin starts
+        // (policy 2) are set with the groups
+        const uint64_t L = d.L;
+        const uint64_t li = (r * L + d.nr - 1) / d.nr;          // ceil(r L / nr)
+        if (li < L && (li * d.nr) / L == r) {
+          flo[q] = static_cast<double>(li) - 1.0;
+          fhi[q] = static_cast<double>(li);
+          seg[q] = SB[i] - d.SB0;
+        }
       }
+    }
+#pragma unroll
+    for (int q = 0; q < kPlanUnroll; ++q) {
+      const PlanCtx d = (G == 1) ? c0 : plan_ctx(desc[gq[q]]);
+      if (flo[q] < fhi[q]) claim_units(d, flo[q], fhi[q], seg[q], cl[q] - d.C0, lane_seg, lane_cum);
+      if (live[q]) A[i0 + q * stride] = wu[q] / d.S;   // a_u of Alg. 1, once per source
     }
   }
+}
+
+__global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
+  if (hdr->status) return;
+  if (hdr->G == 1) lane_plan_sources<true>(hdr);
+  else lane_plan_sources<false>(hdr);
 }
 
 // group -> graph map, the padding lanes (empty: start = (u_end, 0)) and the
@@ -1256,7 +1321,7 @@ __global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out
     const uint64_t wn = in ? words : 0, en = in ? cnt : 0;
     const uint64_t wincl = wave_inclusive<uint64_t>(wn);
     const uint64_t eincl = wave_inclusive<uint64_t>(en);
-    const uint64_t total = uni64(shfl_idx64(wincl, 63));
+    const uint64_t total = lane63_64(wincl);
     sh_wpre[wv][lane] = wincl - wn;
     if (lane == 63) sh_wpre[wv][kLaneGroup] = total;
     sh_src[wv][lane] = s0 - (wincl - wn);

@@ -47,6 +47,7 @@ struct GraphDesc {
   uint64_t hs_off;   // first heavy-table entry
   uint64_t L;        // lanes that carry work
   uint64_t Lm, Zm;   // the first Lm units share the cost [0, Zm); the other L - Lm share [Zm, Z)
+  double um, ut;     // units per cost unit below / from Zm (lane plan only)
   uint64_t NL;       // lanes incl. padding to a multiple of 64
   uint64_t lane_off; // first lane
   uint64_t m;        // edges

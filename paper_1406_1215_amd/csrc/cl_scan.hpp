@@ -1,6 +1,6 @@
 // Device-wide exclusive prefix sums (reduce / scan-of-partials / down-sweep),
 // generic over the element type and over how elements are produced and
-// consumed.  Tiles of kScanThreads x kScanItems consecutive elements.
+// consumed.  Tiles of kScanThreads x ScanItems<T> consecutive elements.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -12,6 +12,21 @@ namespace cl {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr uint64_t kScanTile = static_cast<uint64_t>(kScanThreads) * kScanItems;
+
+// elements per thread of a tile: kScanItems, or 8 for the 24-byte Triple,
+// whose down-sweep holds its tile in registers (fewer registers, more waves)
+template <class T>
+struct ScanItems {
+  static constexpr int value = kScanItems;
+};
+template <>
+struct ScanItems<Triple> {
+  static constexpr int value = 8;
+};
+template <class T>
+constexpr uint64_t scan_tile() {
+  return static_cast<uint64_t>(kScanThreads) * ScanItems<T>::value;
+}
 
 __device__ __forceinline__ uint64_t shfl_up64(uint64_t x, int d) {
   const int lo = __shfl_up(static_cast<int>(static_cast<uint32_t>(x)), d, 64);
@@ -25,6 +40,25 @@ __device__ __forceinline__ uint64_t shfl_idx64(uint64_t x, int src) {
   return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
 }
 
+// DPP move of both halves of a 64-bit value: lanes outside the row / bank
+// masks, and lanes whose source lies outside the row (or the wavefront),
+// read 0.  kCtrl is the DPP control word (row_shr:n = 0x110 + n,
+// wave_shr:1 = 0x138, row_bcast:15 = 0x142, row_bcast:31 = 0x143).
+template <int kCtrl, int kRowMask, int kBankMask>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(x)), kCtrl, kRowMask,
+                                             kBankMask, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(x >> 32)), kCtrl, kRowMask,
+                                             kBankMask, true);
+  return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+}
+
+__device__ __forceinline__ uint64_t lane63_64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(x)), 63);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(x >> 32)), 63);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 template <class T>
 struct ScanTraits;
 
@@ -34,6 +68,9 @@ struct ScanTraits<uint64_t> {
   __device__ static uint64_t add(uint64_t a, uint64_t b) { return a + b; }
   __device__ static uint64_t shfl_up(uint64_t a, int d) { return shfl_up64(a, d); }
   __device__ static uint64_t shfl_idx(uint64_t a, int src) { return shfl_idx64(a, src); }
+  template <int kCtrl, int kRowMask, int kBankMask>
+  __device__ static uint64_t dpp(uint64_t a) { return dpp64<kCtrl, kRowMask, kBankMask>(a); }
+  __device__ static uint64_t lane63(uint64_t a) { return lane63_64(a); }
 };
 
 template <>
@@ -46,7 +83,37 @@ struct ScanTraits<Triple> {
   __device__ static Triple shfl_idx(Triple a, int src) {
     return Triple{shfl_idx64(a.c, src), shfl_idx64(a.k, src), shfl_idx64(a.h, src)};
   }
+  template <int kCtrl, int kRowMask, int kBankMask>
+  __device__ static Triple dpp(Triple a) {
+    return Triple{dpp64<kCtrl, kRowMask, kBankMask>(a.c), dpp64<kCtrl, kRowMask, kBankMask>(a.k),
+                  dpp64<kCtrl, kRowMask, kBankMask>(a.h)};
+  }
+  __device__ static Triple lane63(Triple a) { return Triple{lane63_64(a.c), lane63_64(a.k), lane63_64(a.h)}; }
 };
+
+// Inclusive scan across the 64 lanes of a wavefront with DPP moves (no LDS
+// traffic): three row shifts sum each lane's group of four, shifts by 4 and
+// 8 complete the scan of each row of 16 lanes, and the broadcasts of lanes
+// 15 and 31 carry the row totals into the rows above.
+template <class T>
+__device__ __forceinline__ T wave_inclusive(T v) {
+  using Tr = ScanTraits<T>;
+  const T v0 = v;
+  v = Tr::add(v, Tr::template dpp<0x111, 0xf, 0xf>(v0));   // row_shr:1
+  v = Tr::add(v, Tr::template dpp<0x112, 0xf, 0xf>(v0));   // row_shr:2
+  v = Tr::add(v, Tr::template dpp<0x113, 0xf, 0xf>(v0));   // row_shr:3
+  v = Tr::add(v, Tr::template dpp<0x114, 0xf, 0xe>(v));    // row_shr:4 into lanes 4..15 of a row
+  v = Tr::add(v, Tr::template dpp<0x118, 0xf, 0xc>(v));    // row_shr:8 into lanes 8..15 of a row
+  v = Tr::add(v, Tr::template dpp<0x142, 0xa, 0xf>(v));    // lane 15 of rows 0, 2 into rows 1, 3
+  v = Tr::add(v, Tr::template dpp<0x143, 0xc, 0xf>(v));    // lane 31 into rows 2, 3
+  return v;
+}
+
+// the value of the lane below (0 in lane 0)
+template <class T>
+__device__ __forceinline__ T wave_prev(T v) {
+  return ScanTraits<T>::template dpp<0x138, 0xf, 0xf>(v);   // wave_shr:1
+}
 
 // Exclusive scan of one value per thread across a block of kScanThreads.
 // Returns the exclusive prefix; *total gets the block total.
@@ -56,12 +123,7 @@ __device__ __forceinline__ T block_exclusive(T v, T* total) {
   __shared__ T wave_tot[kScanThreads / 64];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  T inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    T o = Tr::shfl_up(inc, d);
-    if (lane >= d) inc = Tr::add(inc, o);
-  }
+  const T inc = wave_inclusive<T>(v);
   if (lane == 63) wave_tot[wave] = inc;
   __syncthreads();
   T wbase = Tr::zero();
@@ -73,10 +135,8 @@ __device__ __forceinline__ T block_exclusive(T v, T* total) {
   }
   __syncthreads();
   *total = all;
-  // exclusive = inclusive - v, formed as wbase + (inclusive of lanes before)
-  T prev = Tr::shfl_up(inc, 1);
-  if (lane == 0) prev = Tr::zero();
-  return Tr::add(wbase, prev);
+  // exclusive = wbase + (inclusive of the lanes before)
+  return Tr::add(wbase, wave_prev<T>(inc));
 }
 
 // Element producers and consumers.  An In provides
@@ -92,37 +152,25 @@ struct OneGraph {
   __device__ Ctx context(uint32_t) const { return 0; }
 };
 
-// inclusive scan across the 64 lanes of a wavefront
-template <class T>
-__device__ __forceinline__ T wave_inclusive(T v) {
-  using Tr = ScanTraits<T>;
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const T o = Tr::shfl_up(v, d);
-    if (lane >= d) v = Tr::add(v, o);
-  }
-  return v;
-}
-
 // Phase 1: per-tile totals (striped, coalesced loads; the order of the
 // additions does not matter for the integer types scanned on the plan path).
 template <class T, class In>
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(In in, uint64_t N, T* partials) {
   using Tr = ScanTraits<T>;
-  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile;
-  const uint64_t end = (base + kScanTile < N) ? base + kScanTile : N;
+  constexpr int kItems = ScanItems<T>::value;
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * scan_tile<T>();
+  const uint64_t end = (base + scan_tile<T>() < N) ? base + scan_tile<T>() : N;
   const uint32_t g0 = __builtin_amdgcn_readfirstlane(in.graph_of(base));
   const uint32_t g1 = __builtin_amdgcn_readfirstlane(in.graph_of(end - 1));
   T s = Tr::zero();
   if (g0 == g1) {
     const typename In::Ctx c = in.context(g0);
-    for (int r = 0; r < kScanItems; ++r) {
+    for (int r = 0; r < kItems; ++r) {
       const uint64_t idx = base + static_cast<uint64_t>(r) * kScanThreads + threadIdx.x;
       if (idx < end) s = Tr::add(s, in.load(idx, c));
     }
   } else {
-    for (int r = 0; r < kScanItems; ++r) {
+    for (int r = 0; r < kItems; ++r) {
       const uint64_t idx = base + static_cast<uint64_t>(r) * kScanThreads + threadIdx.x;
       if (idx < end) s = Tr::add(s, in.load(idx, in.context(in.graph_of(idx))));
     }
@@ -162,30 +210,29 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_partials(T* partials, uin
 // ctx, value, exclusive prefix) for every element.  Each wavefront owns a
 // contiguous quarter of the tile and walks it 64 elements at a time, so loads
 // and stores are coalesced; its carry-in is the tile's plus the totals of the
-// wavefronts before it.
-template <class T, class In, class Out>
-__global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, Out out, uint64_t N, const T* partials) {
+// wavefronts before it.  A tile inside one graph (kOne) runs an instance with
+// no per-element context loads: with them, every wait for a load in the store
+// loop would also wait for the stores issued before it.
+template <bool kOne, class T, class In, class Out>
+__device__ __forceinline__ void scan_down_tile(In in, Out out, uint64_t base, uint64_t end, uint32_t g0,
+                                               const T* partials) {
   using Tr = ScanTraits<T>;
+  constexpr int kItems = ScanItems<T>::value;
   constexpr int kWaves = kScanThreads / 64;
-  constexpr uint64_t kWaveSpan = static_cast<uint64_t>(kScanItems) * 64;
+  constexpr uint64_t kWaveSpan = static_cast<uint64_t>(kItems) * 64;
   __shared__ T wave_tot[kWaves];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile;
-  const uint64_t end = (base + kScanTile < N) ? base + kScanTile : N;
   const uint64_t wbase = base + wave * kWaveSpan;
-  const uint32_t g0 = __builtin_amdgcn_readfirstlane(in.graph_of(base));
-  const uint32_t g1 = __builtin_amdgcn_readfirstlane(in.graph_of(end - 1));
-  const bool one = (g0 == g1);
   const typename In::Ctx ci = in.context(g0);
   const typename Out::Ctx co = out.context(g0);
-  T vals[kScanItems];
+  T vals[kItems];
   T s = Tr::zero();
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < kItems; ++r) {
     const uint64_t idx = wbase + static_cast<uint64_t>(r) * 64 + lane;
     T v = Tr::zero();
-    if (idx < end) v = one ? in.load(idx, ci) : in.load(idx, in.context(in.graph_of(idx)));
+    if (idx < end) v = kOne ? in.load(idx, ci) : in.load(idx, in.context(in.graph_of(idx)));
     vals[r] = v;
     s = Tr::add(s, v);
   }
@@ -196,29 +243,41 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, Out out, uint
   for (int w = 0; w < kWaves; ++w)
     if (w < wave) carry = Tr::add(carry, wave_tot[w]);
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < kItems; ++r) {
     const uint64_t idx = wbase + static_cast<uint64_t>(r) * 64 + lane;
     const T incl = wave_inclusive<T>(vals[r]);
-    T prev = Tr::shfl_up(incl, 1);
-    if (lane == 0) prev = Tr::zero();
+    const T prev = wave_prev<T>(incl);
     if (idx < end) {
       const T ex = Tr::add(carry, prev);
-      if (one)
+      if (kOne)
         out.store(idx, co, vals[r], ex);
       else
         out.store(idx, out.context(in.graph_of(idx)), vals[r], ex);
     }
-    carry = Tr::add(carry, Tr::shfl_idx(incl, 63));
+    carry = Tr::add(carry, Tr::lane63(incl));
   }
 }
 
-inline uint64_t scan_tiles(uint64_t N) { return (N + kScanTile - 1) / kScanTile; }
+template <class T, class In, class Out>
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, Out out, uint64_t N, const T* partials) {
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * scan_tile<T>();
+  const uint64_t end = (base + scan_tile<T>() < N) ? base + scan_tile<T>() : N;
+  const uint32_t g0 = __builtin_amdgcn_readfirstlane(in.graph_of(base));
+  const uint32_t g1 = __builtin_amdgcn_readfirstlane(in.graph_of(end - 1));
+  if (g0 == g1) scan_down_tile<true, T>(in, out, base, end, g0, partials);
+  else scan_down_tile<false, T>(in, out, base, end, g0, partials);
+}
 
-// Runs the three phases on `stream`; `partials` must hold scan_tiles(N) T's.
+template <class T = uint64_t>
+inline uint64_t scan_tiles(uint64_t N) {
+  return (N + scan_tile<T>() - 1) / scan_tile<T>();
+}
+
+// Runs the three phases on `stream`; `partials` must hold scan_tiles<T>(N) T's.
 template <class T, class In, class Out>
 inline hipError_t device_scan(In in, Out out, uint64_t N, T* partials, hipStream_t stream) {
   if (N == 0) return hipSuccess;
-  const uint64_t nt = scan_tiles(N);
+  const uint64_t nt = scan_tiles<T>(N);
   hipLaunchKernelGGL((k_scan_reduce<T, In>), dim3(static_cast<uint32_t>(nt)), dim3(kScanThreads), 0, stream,
                      in, N, partials);
   hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(kScanThreads), 0, stream, partials, nt);

@@ -34,6 +34,18 @@ struct ScanTraits<Dbl2> {
     return Dbl2{__longlong_as_double(static_cast<long long>(shfl_idx64(static_cast<uint64_t>(__double_as_longlong(x.a)), src))),
                 __longlong_as_double(static_cast<long long>(shfl_idx64(static_cast<uint64_t>(__double_as_longlong(x.b)), src)))};
   }
+  template <int kCtrl, int kRowMask, int kBankMask>
+  __device__ static Dbl2 dpp(Dbl2 x) {   // lanes that read nothing get +0.0
+    auto one = [](double v) {
+      return __longlong_as_double(static_cast<long long>(
+          dpp64<kCtrl, kRowMask, kBankMask>(static_cast<uint64_t>(__double_as_longlong(v)))));
+    };
+    return Dbl2{one(x.a), one(x.b)};
+  }
+  __device__ static Dbl2 lane63(Dbl2 x) {
+    return Dbl2{__longlong_as_double(static_cast<long long>(lane63_64(static_cast<uint64_t>(__double_as_longlong(x.a))))),
+                __longlong_as_double(static_cast<long long>(lane63_64(static_cast<uint64_t>(__double_as_longlong(x.b)))))};
+  }
 };
 
 // suffix sums of w and w^2: element i is w[n-1-i]; exclusive prefix at i is
