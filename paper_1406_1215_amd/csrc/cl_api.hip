@@ -201,15 +201,14 @@ hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* 
   const uint32_t cap = stream_grid_cap();
   hipLaunchKernelGGL(k_heavy_table, dim3(grid_for(h.cap_nh, 256, cap)), dim3(256), 0, s, dhdr);
   hipLaunchKernelGGL(k_lane_plan, dim3(grid_for(h.total_r, 256, cap)), dim3(256), 0, s, dhdr);
-  hipLaunchKernelGGL(k_lane_groups, dim3(grid_for(h.cap_nl / kLaneGroup, 256, cap)), dim3(256), 0, s, dhdr);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
+  hipLaunchKernelGGL(k_lane_groups, dim3(grid_for(h.cap_nl, 256, cap)), dim3(256), 0, s, dhdr);
+  // (the unit queue and the overflow count were cleared with the status)
   if (h.mode == 2) {   // plan only (cl_plan): no lane kernel, no counts
     if (ev0) (void)hipEventRecord(ev0, s);
     if (ev1) (void)hipEventRecord(ev1, s);
     return hipGetLastError();
   }
   if (h.mode == 1) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->overflow, 0u);
     hipError_t e = device_scan<uint64_t>(SlotIn{dhdr}, SlotOut{{}, h.slot_off}, h.cap_nl + 1,
                                          h.slot_scan_tmp, s);
     if (e != hipSuccess) return e;
@@ -239,8 +238,7 @@ hipError_t launch_write(WsHeader* dhdr, const cl_tuning* t, uint32_t* edges, uin
                         uint64_t* graph_offsets, hipStream_t s) {
   const uint32_t cus = std::max<uint32_t>(cus_of_current_device(), 1);
   hipLaunchKernelGGL((k_compact<false>), dim3(cus * 16), dim3(256), 0, s, dhdr, reinterpret_cast<uint2*>(edges), lo,
-                     hi, kNoRows);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
+                     hi, kNoRows);   // also clears the unit queue
   hipLaunchKernelGGL((k_lanes<1>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
                      reinterpret_cast<uint2*>(edges), lo, hi, static_cast<uint32_t*>(nullptr), kNoRows);
   if (graph_offsets) hipLaunchKernelGGL(k_graph_offsets, dim3(16), dim3(256), 0, s, dhdr, graph_offsets);
@@ -541,13 +539,12 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
     ev0 = nullptr;
     ev1 = nullptr;
   }
-  // planned: 1 = counted (cl_count, cl_sample), 2 = plan only (cl_plan); set
-  // on the stream after the lane kernel (the write kernels test it), and
+  // planned: 1 = counted (cl_count, cl_sample; set by the last kernel of the
+  // count, before the write kernels that test it), 2 = plan only (cl_plan);
   // cleared again below if the plan failed
-  const uint32_t flag = (mode == 2) ? 2u : 1u;
   hipError_t eb = launch_plan_back(dhdr, h, t, s, ev0, ev1);
-  if (eb == hipSuccess) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->planned, flag);
+  if (eb == hipSuccess && mode == 2) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->planned, 2u);
     eb = hipGetLastError();
   }
   if (eb == hipSuccess && into) eb = launch_write(dhdr, t, into->edges, 0, into->cap, into->graph_offsets, s);
@@ -653,8 +650,7 @@ cl_status cl_generate_csr(void* ws, const cl_tuning* t, uint32_t* col, uint64_t 
   // one-pass plans: the slots; then the replay of overflowed units (one-pass
   // plans) or of every unit (two-pass plans); then the row offsets
   hipLaunchKernelGGL((k_compact<true>), dim3(cus * 16), dim3(256), 0, s, dhdr, reinterpret_cast<uint2*>(col), 0ull,
-                     cap, rows);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
+                     cap, rows);   // also clears the unit queue
   hipLaunchKernelGGL((k_lanes<4>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
                      reinterpret_cast<uint2*>(col), 0ull, cap, static_cast<uint32_t*>(nullptr), rows);
   CL_TRY(hipGetLastError());

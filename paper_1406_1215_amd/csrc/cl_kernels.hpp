@@ -289,6 +289,8 @@ __global__ void k_reset_status(WsHeader* hdr) {
     hdr->status = 0;
     hdr->total_cand = 0;
     hdr->total_words = 0;
+    hdr->queue = 0;      // the unit queue of the plan's lane kernel
+    hdr->overflow = 0;
   }
 }
 
@@ -708,25 +710,24 @@ __global__ void __launch_bounds__(256) k_lane_plan(const WsHeader* hdr) {
 }
 
 // group -> graph map, the padding lanes (empty: start = (u_end, 0)) and the
-// starts of round-robin units
+// starts of round-robin units; one thread per lane (lane_off is a multiple
+// of the group size, so a group's first lane is a graph-relative multiple)
 __global__ void __launch_bounds__(256) k_lane_groups(const WsHeader* hdr) {
   if (hdr->status) return;
   const GraphDesc* desc = hdr->desc;
   const uint32_t G = hdr->G;
-  const uint64_t ngroups = hdr->total_nl / kLaneGroup;
+  const uint64_t nl = hdr->total_nl;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t q = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; q < ngroups; q += stride) {
-    const uint64_t l0 = q * kLaneGroup;
-    const uint32_t g = find_graph(G, l0, [&](uint32_t x) { return desc[x].lane_off; });
+  for (uint64_t l = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; l < nl; l += stride) {
+    const uint32_t g = (G == 1) ? 0u : find_graph(G, l, [&](uint32_t x) { return desc[x].lane_off; });
     const GraphDesc& d = desc[g];
-    hdr->group_graph[q] = g;
-    for (uint64_t li = (l0 - d.lane_off); li < (l0 - d.lane_off) + kLaneGroup; ++li) {
-      if (li < d.L && d.policy == 2) {
-        hdr->lane_seg[d.lane_off + li] = static_cast<uint32_t>(li);   // round robin: first segment i
-      } else if (li >= d.L) {
-        hdr->lane_seg[d.lane_off + li] = static_cast<uint32_t>(d.SB1 - d.SB0);
-        if (hdr->lane_cum) hdr->lane_cum[d.lane_off + li] = d.C1 - d.C0;
-      }
+    const uint64_t li = l - d.lane_off;
+    if (l % kLaneGroup == 0) hdr->group_graph[l / kLaneGroup] = g;
+    if (li < d.L && d.policy == 2) {
+      hdr->lane_seg[l] = static_cast<uint32_t>(li);   // round robin: first segment i
+    } else if (li >= d.L) {
+      hdr->lane_seg[l] = static_cast<uint32_t>(d.SB1 - d.SB0);
+      if (hdr->lane_cum) hdr->lane_cum[l] = d.C1 - d.C0;
     }
   }
 }
@@ -1292,11 +1293,14 @@ constexpr int kCompactSteps = 8;
 // source inside an instruction adds its length to rows[q_g + u] (the first
 // lane of the run does, a run being a stretch of consecutive edge lanes).
 template <bool kCsr>
-__global__ void __launch_bounds__(256) k_compact(const WsHeader* hdr, uint2* out, uint64_t lo, uint64_t hi,
+__global__ void __launch_bounds__(256) k_compact(WsHeader* hdr, uint2* out, uint64_t lo, uint64_t hi,
                                                  unsigned long long* rows) {
   __shared__ uint64_t sh_wpre[4][kLaneGroup + 1];   // stream position of each unit's first word, then the total
   __shared__ uint64_t sh_src[4][kLaneGroup];        // slot index of stream word t of unit j: sh_src[j] + t
   __shared__ uint64_t sh_dst[4][kLaneGroup];        // output position of stream edge k of unit j: sh_dst[j] + k
+  // the unit queue of the replay kernel that follows (no lane kernel runs
+  // during this one), reset for every plan kind
+  if (blockIdx.x == 0 && threadIdx.x == 0) hdr->queue = 0;
   if (hdr->status || hdr->mode != 1 || !hdr->planned) return;
   const uint64_t ngroups = uni64(hdr->total_nl) / kLaneGroup;
   const int lane = threadIdx.x & 63;
@@ -1435,7 +1439,10 @@ __global__ void __launch_bounds__(256) k_graph_edges(WsHeader* hdr, uint64_t* m_
     }
     if (m_dev) m_dev[g] = d.m;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) hdr->total_m = hdr->status ? 0 : hdr->lane_pos[hdr->total_nl];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    hdr->total_m = hdr->status ? 0 : hdr->lane_pos[hdr->total_nl];
+    hdr->planned = hdr->status ? 0u : 1u;   // counted: the write kernels may run
+  }
 }
 
 __global__ void __launch_bounds__(256) k_graph_offsets(const WsHeader* hdr, uint64_t* go) {
