@@ -52,7 +52,7 @@ typedef int32_t cl_status;
 #define CL_ERR_TOO_LARGE   (-5)  /* n >= 2^32 (node ids are uint32) */
 #define CL_ERR_WORKSPACE   (-6)  /* workspace too small; the required size is reported */
 #define CL_ERR_CAPACITY    (-7)  /* a size exceeded what the workspace was laid out for */
-#define CL_ERR_DEVICE      (-8)  /* a HIP runtime error */
+#define CL_ERR_DEVICE      (-8)  /* a HIP runtime error, or an internal check failed on the device */
 #define CL_ERR_NOT_PLANNED (-9)  /* workspace does not hold a plan from cl_count */
 
 /* One generation task: Create-Edges(w, S, [u_begin, u_end)) of Alg. 1. */

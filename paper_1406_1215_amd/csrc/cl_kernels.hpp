@@ -546,8 +546,9 @@ __device__ __forceinline__ void claim_units(const PlanCtx& p, double flo, double
 // --------------------------------------------------------------------------
 // heavy-segment table (one thread per heavy segment), and the unit starts
 // inside heavy segments.  The graph's fields are read once per thread into
-// registers (before any store), and the two boundary searches of a segment
-// advance in lockstep so that their loads overlap.
+// registers (before any store).  Each thread searches its segment's start;
+// the end comes from the next lane, except in a wavefront's last lane, whose
+// two searches advance in lockstep.
 // --------------------------------------------------------------------------
 struct HeavyCtx {
   uint64_t hs_off, H, r_off, SB0, u_begin, q_off, Qbase, Qn, n;
@@ -594,9 +595,14 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
     // (b_0 = u + 1; the last segment ends at n)
     auto target = [&](uint64_t kk) { return base + kk * (Dm / K) + (kk * (Dm % K)) / K; };
     const uint64_t t0 = target(k), t1 = target(k + 1);
+    // The end of segment k is the start of segment k + 1, which the next lane
+    // searches (table entry h + 1) unless this is the wavefront's last lane or
+    // the table's last entry; the last segment of a source ends at n.
+    const int lane = threadIdx.x & 63;
+    const bool own_end = (k + 1 < K) && (lane == 63 || h + 1 >= NH);
     uint64_t lo0 = u + 1, hi0 = c.n, lo1 = u + 1, hi1 = c.n;
     if (k == 0) hi0 = lo0;
-    if (k + 1 >= K) lo1 = hi1;
+    if (!own_end) lo1 = hi1;
     while (lo0 < hi0 || lo1 < hi1) {
       const uint64_t m0 = lo0 + ((hi0 - lo0) >> 1);
       const uint64_t m1 = lo1 + ((hi1 - lo1) >> 1);
@@ -609,8 +615,9 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
         if (q1 >= t1) hi1 = m1; else lo1 = m1 + 1;
       }
     }
-    hseg[h] = u32x4{static_cast<uint32_t>(u), static_cast<uint32_t>(k), static_cast<uint32_t>(lo0),
-                    static_cast<uint32_t>(lo1)};
+    const uint32_t next_start = static_cast<uint32_t>(__shfl_down(static_cast<int>(lo0), 1, 64));
+    const uint32_t send = (k + 1 >= K) ? static_cast<uint32_t>(c.n) : own_end ? static_cast<uint32_t>(lo1) : next_start;
+    hseg[h] = u32x4{static_cast<uint32_t>(u), static_cast<uint32_t>(k), static_cast<uint32_t>(lo0), send};
     const PlanCtx p = (G == 1) ? p0 : plan_ctx(desc[g]);
     if (p.equal_cost_units()) {
       // segment k's share (b_k, b_k+1] of the source's cost (C_u, C_u+1]
@@ -1180,6 +1187,10 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
           unit = mine;
           s.sg = lane_seg[unit];
           s.sg_end = (rr || unit + 1 >= unit_end) ? nseg : lane_seg[unit + 1];
+          if (s.sg > s.sg_end || s.sg_end > nseg) {   // never for a valid plan: flagged, nothing read
+            atomicOr(&hdr->status, static_cast<uint32_t>(kStPlan));
+            s.sg = s.sg_end = 0;
+          }
           s.inseg = false;
           if constexpr (kMode == 0) {
             em = Emit{0u};

@@ -26,6 +26,7 @@ enum : uint32_t {
   kStBadS = 1u << 3,        // S < w_0, or 0 < w_0 < 2^-960
   kStCapacity = 1u << 4,    // a size exceeded the capacity frozen in the workspace
   kStCostOverflow = 1u << 5,
+  kStPlan = 1u << 6,        // a work unit's segment range out of order or past the graph (internal error)
 };
 
 struct GraphDesc {
