@@ -160,6 +160,30 @@ def test_batched_tasks_equal_single_tasks(planner, cg):
 
 
 @pytest.mark.parametrize("planner", PLANNERS)
+def test_batched_heavy_graphs_bit_exact(planner, cg):
+    """Several graphs with split sources in one plan: their heavy segments sit
+    side by side in one table (wavefronts straddle graphs), and each graph's
+    unit starts are placed on its own segments."""
+    import torch
+    shapes = [(3000, 60.0), (9000, 25.0), (700, 300.0), (15000, 40.0), (64, 64.0), (5000, 120.0)]
+    tasks, wants = [], []
+    for i, (n, scale) in enumerate(shapes):
+        w = _heavy(n, 90 + i, scale)
+        S = O.exact_sum(w)
+        e, m, _, _ = O.generate(w, S, 300 + i)
+        wants.append(e)
+        tasks.append(cg.Task(_to_dev(w), S, 300 + i))
+    plan = getattr(cg, planner)(tasks)
+    assert cg.cl_plan_info(plan)["heavy_segments"] > 64
+    assert plan.m == [x.shape[0] for x in wants]
+    go = torch.zeros(len(tasks) + 1, dtype=torch.int64, device="cuda:0")
+    e = _edges_np(cg.cl_generate(plan, graph_offsets=go))
+    off = go.cpu().numpy()
+    for i, want in enumerate(wants):
+        assert np.array_equal(e[off[i]:off[i + 1]], want), i
+
+
+@pytest.mark.parametrize("planner", PLANNERS)
 def test_write_windows(planner, cg):
     import torch
     w = _heavy(40000, 80, 30.0)
