@@ -211,8 +211,15 @@ __global__ void __launch_bounds__(64) k_sum_finalize(const unsigned long long* b
     acc += part;
     carry += (acc < part) ? 1 : 0;
   };
-  for (int b0 = 0; b0 < 2 * kBins; b0 += 64) {
-    const uint64_t mine = bins[b0 + L];
+  // all bin words are loaded first (one round trip instead of one per chunk)
+  constexpr int kChunks = 2 * kBins / 64;
+  uint64_t words[kChunks];
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) words[c] = bins[c * 64 + L];
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    const int b0 = c * 64;
+    const uint64_t mine = words[c];
     uint64_t nz = __ballot(mine != 0);
     while (nz) {
       const int k = __ffsll(static_cast<long long>(nz)) - 1;
