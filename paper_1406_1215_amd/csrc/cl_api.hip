@@ -89,7 +89,10 @@ FixedLayout fixed_layout(const cl_graph* g, uint32_t G) {
   L.total_r = tr;
   // scan partials: Triple tiles of the source scan or u64 tiles of the Q scan
   L.scan_elems = std::max<uint64_t>(scan_tiles(tq), 3 * scan_tiles<Triple>(tr)) + 8;
+  // the edge counts follow the header, so that one copy reads both back
   uint64_t off = align_up(sizeof(WsHeader));
+  L.off_m = off;
+  off = align_up(off + 8 * G);
   L.off_desc = off;
   off = align_up(off + sizeof(GraphDesc) * G);
   L.off_Q = off;
@@ -102,8 +105,6 @@ FixedLayout fixed_layout(const cl_graph* g, uint32_t G) {
   off = align_up(off + 8 * tr);
   L.off_scan = off;
   off = align_up(off + 8 * L.scan_elems);
-  L.off_m = off;
-  off = align_up(off + 8 * G);
   L.bytes = off;
   return L;
 }
@@ -288,11 +289,13 @@ cl_status cl_weight_sum(const double* w, uint64_t n, void* ws, uint64_t ws_bytes
   hipLaunchKernelGGL((k_validate<true>), dim3(grid_for(n + 1, 256, cap)), dim3(256), 0, s, d, 1u, n + 1, bins);
   hipLaunchKernelGGL(k_sum_finalize, dim3(1), dim3(64), 0, s, bins, S_dev, &d->status);
   CL_TRY(hipGetLastError());
-  double Sh = 0.0;
-  uint32_t st = 0;
-  CL_TRY(hipMemcpyAsync(&Sh, S_dev, sizeof(double), hipMemcpyDeviceToHost, s));
-  CL_TRY(hipMemcpyAsync(&st, &d->status, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  // S and the status word, stored side by side by the finaliser: one read-back
+  uint64_t res[2] = {0, 0};
+  CL_TRY(hipMemcpyAsync(res, S_dev, sizeof(res), hipMemcpyDeviceToHost, s));
   CL_TRY(hipStreamSynchronize(s));
+  double Sh;
+  memcpy(&Sh, &res[0], sizeof(Sh));
+  uint32_t st = static_cast<uint32_t>(res[1]);
   st &= ~static_cast<uint32_t>(kStBadS);   // no S given: the w_0 / S conditions do not apply
   if (st) return status_error(st);
   *S_out = Sh;
@@ -549,10 +552,16 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
   }
   if (eb == hipSuccess && into) eb = launch_write(dhdr, t, into->edges, 0, into->cap, into->graph_offsets, s);
   float lane_ms = -1.0f;
-  if (eb == hipSuccess && hipMemcpyAsync(m_out, h.m_dev, 8ull * G, hipMemcpyDeviceToHost, s) == hipSuccess &&
-      hipMemcpyAsync(&back, dhdr, sizeof(back), hipMemcpyDeviceToHost, s) == hipSuccess &&
-      hipStreamSynchronize(s) == hipSuccess && ev0) {
-    if (hipEventElapsedTime(&lane_ms, ev0, ev1) != hipSuccess) {
+  // the header and the edge counts in one read-back
+  std::vector<unsigned char> head(F.off_m + 8ull * G);
+  if (eb == hipSuccess) {
+    eb = hipMemcpyAsync(head.data(), dhdr, head.size(), hipMemcpyDeviceToHost, s);
+    if (eb == hipSuccess) eb = hipStreamSynchronize(s);
+  }
+  if (eb == hipSuccess) {
+    memcpy(&back, head.data(), sizeof(back));
+    memcpy(m_out, head.data() + F.off_m, 8ull * G);
+    if (ev0 && hipEventElapsedTime(&lane_ms, ev0, ev1) != hipSuccess) {
       lane_ms = -1.0f;
       (void)hipGetLastError();   // leave no error behind for the caller's next HIP call
     }

@@ -195,6 +195,7 @@ __global__ void __launch_bounds__(256) k_validate(GraphDesc* desc, uint32_t G, u
 // Rounds sum_b (hi_b 2^32 + lo_b) 2^(b-1) * 2^-1074 to the nearest double
 // (ties to even).  One wavefront: lane L owns limb L (bits [64 L, 64 L + 64))
 // of the big integer T; 36 limbs cover 2^2304.  Zero bins are skipped.
+// S_out[0] gets S and S_out[1] (as a 64-bit word) the status flags.
 constexpr int kLimbs = 36;
 
 __global__ void __launch_bounds__(64) k_sum_finalize(const unsigned long long* bins, double* S_out,
@@ -242,6 +243,7 @@ __global__ void __launch_bounds__(64) k_sum_finalize(const unsigned long long* b
   auto limb = [&](int l) -> uint64_t { return (l >= 0 && l < kLimbs) ? shfl_idx64(T, l) : 0ull; };
   const uint64_t nzl = __ballot(L < kLimbs && T != 0);
   double S;
+  bool inf_sum = false;   // the sum rounds past the largest double
   if (nzl == 0) {
     S = 0.0;
   } else {
@@ -278,14 +280,24 @@ __global__ void __launch_bounds__(64) k_sum_finalize(const unsigned long long* b
       }
       if (e >= 2047) {
         S = __longlong_as_double(0x7FF0000000000000ll);
-        if (L == 0) atomicOr(status, kStNonfinite);
+        inf_sum = true;
       } else {
         S = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(e) << 52) |
                                                         (mant & 0x000FFFFFFFFFFFFFull)));
       }
     }
   }
-  if (L == 0) *S_out = S;
+  if (L == 0) {
+    // the validation kernel's flags (an earlier launch) and this one's; the
+    // status word is also stored beside S, so that one read returns both
+    uint32_t st = *status;
+    if (inf_sum) {
+      st |= kStNonfinite;
+      atomicOr(status, kStNonfinite);
+    }
+    S_out[0] = S;
+    reinterpret_cast<unsigned long long*>(S_out)[1] = st;
+  }
 }
 
 // status words are cleared at the start of every plan (a replayed graph
