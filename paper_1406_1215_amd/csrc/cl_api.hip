@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <utility>
 #include <vector>
 
 #include "clgen.h"
@@ -434,6 +435,38 @@ struct IntoOut {
   uint64_t* graph_offsets;
 };
 
+// The pair of events that times the lane kernel: created once per thread
+// and device and reused by every plan on them (a plan synchronises its
+// stream before reading the pair, so no record is pending at the next one).
+// Both null if they cannot be created.
+static void lane_events(hipEvent_t* e0, hipEvent_t* e1) {
+  static thread_local std::vector<std::pair<hipEvent_t, hipEvent_t>> cache;
+  *e0 = nullptr;
+  *e1 = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (cache.size() <= static_cast<size_t>(dev)) cache.resize(static_cast<size_t>(dev) + 1, {nullptr, nullptr});
+  auto& p = cache[static_cast<size_t>(dev)];
+  if (!p.first) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) {
+      (void)hipGetLastError();
+      return;
+    }
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      (void)hipGetLastError();
+      return;
+    }
+    p = {a, b};
+  }
+  *e0 = p.first;
+  *e1 = p.second;
+}
+
 static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes,
                              uint64_t* m_out, uint64_t* ws_required, void* stream, uint32_t mode,
                              const IntoOut* into = nullptr) {
@@ -488,8 +521,11 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
   h.scan_tmp = reinterpret_cast<uint64_t*>(base + F.off_scan);
   h.scan_tmp_elems = F.scan_elems;
   h.m_dev = reinterpret_cast<uint64_t*>(base + F.off_m);
-  CL_TRY(hipMemcpyAsync(h.desc, desc.data(), sizeof(GraphDesc) * G, hipMemcpyHostToDevice, s));
-  CL_TRY(hipMemcpyAsync(dhdr, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  // header, edge counts (zero) and descriptors in one upload
+  std::vector<unsigned char> up(F.off_desc + sizeof(GraphDesc) * G, 0);
+  memcpy(up.data(), &h, sizeof(h));
+  memcpy(up.data() + F.off_desc, desc.data(), sizeof(GraphDesc) * G);
+  CL_TRY(hipMemcpyAsync(dhdr, up.data(), up.size(), hipMemcpyHostToDevice, s));
   CL_TRY(launch_plan_front(dhdr, h, G, s));
   WsHeader back{};
   CL_TRY(hipMemcpyAsync(&back, dhdr, sizeof(back), hipMemcpyDeviceToHost, s));
@@ -536,12 +572,7 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
   CL_TRY(hipMemcpyAsync(dhdr, &h, sizeof(h), hipMemcpyHostToDevice, s));
   // the lane kernel is timed with HIP events on the caller's stream
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
-  if (ev0 && hipEventCreate(&ev1) != hipSuccess) {
-    (void)hipEventDestroy(ev0);
-    ev0 = nullptr;
-    ev1 = nullptr;
-  }
+  lane_events(&ev0, &ev1);
   // planned: 1 = counted (cl_count, cl_sample; set by the last kernel of the
   // count, before the write kernels that test it), 2 = plan only (cl_plan);
   // cleared again below if the plan failed
@@ -566,8 +597,6 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
       (void)hipGetLastError();   // leave no error behind for the caller's next HIP call
     }
   }
-  if (ev0) (void)hipEventDestroy(ev0);
-  if (ev1) (void)hipEventDestroy(ev1);
   if (eb != hipSuccess) return CL_ERR_DEVICE;
   if (back.status) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->planned, 0u);
