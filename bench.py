@@ -147,12 +147,13 @@ def main():
     plan = None
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    sum_ws = torch.empty(cg.cl_weight_sum_workspace(w.numel()), dtype=torch.uint8, device=dev)
 
     def step(fused=True):
         """One step; with an output buffer from an earlier step, the plan, the
         one pass and the expansion run in one call (cl_sample_into)."""
         nonlocal edges, plan
-        S = cg.cl_weight_sum(w)
+        S = cg.cl_weight_sum(w, ws=sum_ws)
         if fused and edges is not None:
             plan, fits = cg.cl_sample_into([cg.Task(w, S, seed)], edges, ws=plan.ws)
             if fits:

@@ -134,13 +134,22 @@ def _f64(w: torch.Tensor) -> torch.Tensor:
 
 
 # ---------------------------------------------------------------- exact sum
-def cl_weight_sum(w: torch.Tensor, stream=None) -> float:
-    """S = sum(w), exactly rounded (Alg. 1, first line)."""
+def cl_weight_sum_workspace(n: int) -> int:
+    """Workspace bytes cl_weight_sum needs for n weights."""
+    need = _U64(0)
+    _check(lib().cl_weight_sum_workspace(int(n), ctypes.byref(need)), "cl_weight_sum_workspace")
+    return int(need.value)
+
+
+def cl_weight_sum(w: torch.Tensor, stream=None, ws: Optional[torch.Tensor] = None) -> float:
+    """S = sum(w), exactly rounded (Alg. 1, first line).  ws: a uint8 device
+    tensor to reuse as the workspace (allocated here when None or too small)."""
     L = lib()
     w = _f64(w)
     need = _U64(0)
     _check(L.cl_weight_sum_workspace(w.numel(), ctypes.byref(need)), "cl_weight_sum_workspace")
-    ws = _ws(need.value, w.device)
+    if ws is None or ws.numel() < need.value or ws.device != w.device:
+        ws = _ws(need.value, w.device)
     out = ctypes.c_double(0.0)
     _check(L.cl_weight_sum(_ptr(w), w.numel(), _ptr(ws), ws.numel(), ctypes.byref(out), _stream(stream)),
            "cl_weight_sum")

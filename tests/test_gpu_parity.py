@@ -47,13 +47,16 @@ def test_weight_sum_is_exact(cg):
              # round half to even, with and without a sticky bit far below
              np.array([2.0 ** 53, 1.0]), np.array([2.0 ** 53 + 2, 1.0]), np.array([2.0 ** 53, 1.0, 2.0 ** -1000]),
              np.array([2.0 ** 1000, 2.0 ** 947, 5e-324]), np.array([2.0 ** 1000, 2.0 ** 947])]
-    for w in cases:
-        wd = _to_dev(w)
-        if not np.all(np.isfinite(np.sum(w))):
-            with pytest.raises(cg.ClError):
-                cg.cl_weight_sum(wd)
-            continue
-        assert cg.cl_weight_sum(wd) == O.exact_sum(w)
+    import torch
+    shared = torch.empty(cg.cl_weight_sum_workspace(1 << 20), dtype=torch.uint8, device="cuda:0")
+    for ws in (None, shared):   # a fresh workspace per call, then one reused by every case
+        for w in cases:
+            wd = _to_dev(w)
+            if not np.all(np.isfinite(np.sum(w))):
+                with pytest.raises(cg.ClError):
+                    cg.cl_weight_sum(wd, ws=ws)
+                continue
+            assert cg.cl_weight_sum(wd, ws=ws) == O.exact_sum(w)
 
 
 @pytest.mark.parametrize("planner", PLANNERS)
