@@ -183,8 +183,7 @@ uint32_t persistent_grid(const cl_tuning* t) {
 // quantised prefix, per-source prefixes, per-graph sizes
 hipError_t launch_plan_front(WsHeader* dhdr, const WsHeader& h, uint32_t G, hipStream_t s) {
   const uint32_t cap = stream_grid_cap();
-  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(256), 0, s, dhdr);
-  hipLaunchKernelGGL(k_graph_init, dim3((G + 255) / 256), dim3(256), 0, s, h.desc, G);
+  hipLaunchKernelGGL(k_plan_init, dim3((G + 255) / 256), dim3(256), 0, s, dhdr);
   hipLaunchKernelGGL((k_validate<false>), dim3(grid_for(h.total_q, 256, cap)), dim3(256), 0, s, h.desc, G,
                      h.total_q, kNoRows);
   hipError_t e = device_scan<uint64_t>(QIn{h.desc, G}, QOut{h.desc, G, h.Q}, h.total_q, h.scan_tmp, s);

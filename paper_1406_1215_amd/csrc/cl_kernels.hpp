@@ -300,30 +300,37 @@ __global__ void __launch_bounds__(64) k_sum_finalize(const unsigned long long* b
   }
 }
 
-// status words are cleared at the start of every plan (a replayed graph
-// starts from a clean state)
-__global__ void k_reset_status(WsHeader* hdr) {
-  for (uint32_t g = threadIdx.x; g < hdr->G; g += blockDim.x) hdr->desc[g].status = 0;
-  if (threadIdx.x == 0) {
+// a graph's quantisation scale 2^32 / w_0 (0 when w_0 = 0)
+__device__ __forceinline__ void graph_init(GraphDesc& d) {
+  const double w0 = (d.n > 0) ? d.w[0] : 0.0;
+  d.qscale = (w0 > 0.0) ? (4294967296.0 / w0) : 0.0;
+}
+
+__global__ void k_graph_init(GraphDesc* desc, uint32_t G) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  graph_init(desc[g]);
+}
+
+// the start of a plan: cleared status words and counters (a replayed graph
+// starts from a clean state) and each graph's quantisation scale
+__global__ void k_plan_init(WsHeader* hdr) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) {
     hdr->status = 0;
     hdr->total_cand = 0;
     hdr->total_words = 0;
     hdr->queue = 0;      // the unit queue of the plan's lane kernel
     hdr->overflow = 0;
   }
+  if (g >= hdr->G) return;
+  hdr->desc[g].status = 0;
+  graph_init(hdr->desc[g]);
 }
 
 // --------------------------------------------------------------------------
 // quantised prefix Q, all graphs in one scan
 // --------------------------------------------------------------------------
-__global__ void k_graph_init(GraphDesc* desc, uint32_t G) {
-  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= G) return;
-  GraphDesc& d = desc[g];
-  const double w0 = (d.n > 0) ? d.w[0] : 0.0;
-  d.qscale = (w0 > 0.0) ? (4294967296.0 / w0) : 0.0;
-}
-
 struct QIn {
   const GraphDesc* desc;
   uint32_t G;
