@@ -210,10 +210,9 @@ hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* 
     return hipGetLastError();
   }
   if (h.mode == 1) {
-    hipError_t e = device_scan<uint64_t>(SlotIn{dhdr}, SlotOut{{}, h.slot_off}, h.cap_nl + 1,
-                                         h.slot_scan_tmp, s);
+    hipError_t e = device_scan<uint64_t>(SlotIn{dhdr}, SlotOut{{}, h.slot_off, h.slot_cap, dhdr}, h.cap_nl + 1,
+                                         h.slot_scan_tmp, s);   // also checks the total against the capacity
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_slot_check, dim3(1), dim3(1), 0, s, dhdr);
     if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL((k_lanes<2>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
                        static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr), kNoRows);

@@ -1299,14 +1299,18 @@ struct SlotIn {
   }
 };
 
+// the slot offsets; the total (offset at unit total_nl) is checked against
+// the slots' capacity (the offsets are non-decreasing, so only offsets above
+// the capacity look up total_nl)
 struct SlotOut : OneGraph {
   uint64_t* off;
-  __device__ void store(uint64_t i, Ctx, uint64_t, uint64_t ex) const { off[i] = ex; }
+  uint64_t slot_cap;
+  WsHeader* hdr;
+  __device__ void store(uint64_t i, Ctx, uint64_t, uint64_t ex) const {
+    off[i] = ex;
+    if (ex > slot_cap && i == hdr->total_nl) atomicOr(&hdr->status, kStCapacity);
+  }
 };
-
-__global__ void k_slot_check(WsHeader* hdr) {
-  if (hdr->slot_off[hdr->total_nl] > hdr->slot_cap) atomicOr(&hdr->status, kStCapacity);
-}
 
 // Expands every unit's slot words into (u, v) pairs at the unit's place in
 // the output window [lo, hi).  One wavefront per group of 64 units, which it

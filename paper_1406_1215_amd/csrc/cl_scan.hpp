@@ -11,7 +11,6 @@ namespace cl {
 
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
-constexpr uint64_t kScanTile = static_cast<uint64_t>(kScanThreads) * kScanItems;
 
 // elements per thread of a tile: kScanItems, or 8 for the 24-byte Triple,
 // whose down-sweep holds its tile in registers (fewer registers, more waves)
@@ -181,23 +180,27 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(In in, uint64_t N,
 }
 
 // Phase 2: exclusive scan of the tile totals in place (one block; each
-// thread owns kScanItems consecutive totals of a chunk).
+// thread owns kPartItems consecutive totals of a chunk: 24, so that the
+// 2048-element Triple tiles of 1e7 sources fit one chunk).
+constexpr int kPartItems = 24;
+
 template <class T>
 __global__ void __launch_bounds__(kScanThreads) k_scan_partials(T* partials, uint64_t ntiles) {
   using Tr = ScanTraits<T>;
+  constexpr uint64_t kChunk = static_cast<uint64_t>(kScanThreads) * kPartItems;
   T carry = Tr::zero();
-  for (uint64_t chunk = 0; chunk < ntiles; chunk += kScanTile) {
-    const uint64_t base = chunk + static_cast<uint64_t>(threadIdx.x) * kScanItems;
-    T vals[kScanItems];
+  for (uint64_t chunk = 0; chunk < ntiles; chunk += kChunk) {
+    const uint64_t base = chunk + static_cast<uint64_t>(threadIdx.x) * kPartItems;
+    T vals[kPartItems];
     T s = Tr::zero();
-    for (int i = 0; i < kScanItems; ++i) {
+    for (int i = 0; i < kPartItems; ++i) {
       const uint64_t idx = base + i;
       vals[i] = (idx < ntiles) ? partials[idx] : Tr::zero();
       s = Tr::add(s, vals[i]);
     }
     T tot;
     T ex = Tr::add(carry, block_exclusive<T>(s, &tot));
-    for (int i = 0; i < kScanItems; ++i) {
+    for (int i = 0; i < kPartItems; ++i) {
       const uint64_t idx = base + i;
       if (idx < ntiles) partials[idx] = ex;
       ex = Tr::add(ex, vals[i]);
