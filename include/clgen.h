@@ -88,7 +88,7 @@ typedef struct cl_tuning {
 } cl_tuning;
 
 /* ---------------------------------------------------------------------------
- * S <- sum_k w_k (Alg. 1, first line; Sec. 4 "parallel sum").  Returns the
+ * S <- sum_k w_k (Alg. 1, first line; Sec. 4 forms it by a parallel sum).  Returns the
  * exactly rounded sum (the real sum rounded once to nearest-even), which does
  * not depend on the summation order.  Also validates w (sorted, >= 0, finite).
  * ws: device workspace of cl_weight_sum_workspace() bytes.  S_out: host.
@@ -175,7 +175,8 @@ cl_status cl_sample_into(const cl_graph* g /* host, G entries */, uint32_t G, co
                          uint64_t* ws_required /* host, may be NULL */, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Generation, write pass: for a plan of cl_count, replays the planned lanes
+ * Generation, write pass: the output E of Create-Edges (Sec. 3, Alg. 1) for
+ * every planned task.  For a plan of cl_count, replays the planned lanes
  * with the same random words; for a plan of cl_sample, expands the lanes'
  * slot words (and replays the lanes whose slot overflowed).  Either way it
  * writes every edge whose position in the batch output lies in
@@ -183,16 +184,22 @@ cl_status cl_sample_into(const cl_graph* g /* host, G entries */, uint32_t G, co
  * (u, v).  Task g's edges occupy positions [off_g, off_g + m_g), off_g = sum of
  * m_h for h < g.  graph_offsets (device, G + 1 entries, may be NULL) receives
  * off_0..off_{G-1} and the total.  Writing the output in windows (slabs)
- * costs each window only the lanes that overlap it.  Asynchronous.
- * ws must hold the plan of a successful cl_count, cl_sample or cl_sample_into
- * (same inputs, unchanged).
+ * costs each window only the lanes that overlap it (the windows are a
+ * project addition: they stream an output larger than one buffer, and the
+ * storage of a window is left out of the generation time, as Sec. 5 leaves
+ * out I/O).  Asynchronous.
+ * Precondition: ws holds the plan of a successful cl_count, cl_sample or
+ * cl_sample_into (same inputs, unchanged).  The call does not read the plan
+ * back, so it cannot report a workspace that holds no such plan: on a plan
+ * of cl_plan (no counts), or a failed plan, its kernels return at once and
+ * nothing is written.  cl_plan_info reports the state of a workspace.
  * ------------------------------------------------------------------------- */
 cl_status cl_generate(void* ws, const cl_tuning* t, uint32_t* edges, uint64_t edge_begin, uint64_t cap,
                       uint64_t* graph_offsets, void* stream);
 
 /* ---------------------------------------------------------------------------
  * The same edges as compressed sparse rows (the generator's output consumed
- * on the fly, Sec. 5): col[pos] = v for the edge (u, v) at batch position pos
+ * on the fly, as Sec. 4 suggests for analysis without disk I/O): col[pos] = v for the edge (u, v) at batch position pos
  * (4 bytes per edge instead of 8), and row_ptr[q_g + u] = the batch position
  * of the first edge of source u of task g, q_g = sum over earlier tasks h of
  * (n_h + 1), so that the targets of u are col[row_ptr[q_g + u] ..
@@ -217,7 +224,8 @@ cl_status cl_plan(const cl_graph* g /* host, G entries */, uint32_t G, const cl_
 
 /* ---------------------------------------------------------------------------
  * Degrees of the planned graphs without storing any edge (the generator's
- * output analysed on the fly, Sec. 5 "generate and analyse without I/O"):
+ * output analysed on the fly, which Sec. 4 names as a use of generation
+ * without disk I/O):
  * runs the planned lanes once more with the same random words and adds, for
  * every kept edge (u, v), 1 to deg[q_g + u] and deg[q_g + v], where
  * q_g = sum over earlier tasks h of (n_h + 1) (for one task, deg[0 .. n)).
@@ -231,7 +239,7 @@ cl_status cl_degrees(void* ws, const cl_tuning* t, uint32_t* deg, uint64_t deg_l
 
 /* Totals of the plan in ws (host outputs, each may be NULL; synchronises).
  * lanes includes the padding to whole wavefronts; candidates is the number of
- * candidates the lane kernel visited (the "edges + sources" work of Eq. 2-4,
+ * candidates the lane kernel visited (the edge-plus-source work of Eq. 2-4,
  * rejections included); lane_kernel_ms is the duration of that kernel
  * (count pass or one pass), timed by HIP events on the caller's stream and
  * stored on that stream after the planning call returns (read it there);
@@ -251,7 +259,9 @@ cl_status cl_plan_info(const void* ws, uint64_t* lanes, uint64_t* heavy_segments
 cl_status cl_hash_edges(const uint32_t* edges, uint64_t m, uint64_t index_base, uint64_t* acc, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Batched generation as one replayable HIP graph: records the whole path
+ * Batched generation as one replayable HIP graph (a project addition: each
+ * of the G tasks is Create-Edges(w, S, V) of Sec. 3, Alg. 1, and the batch
+ * output is their concatenation, as from G calls): records the whole path
  * (validation, prefix, plan, count or one pass, offsets, output) for the G
  * tasks planned in ws by a preceding cl_count or cl_sample (same g), with the
  * sizes of that plan, on a
@@ -259,6 +269,8 @@ cl_status cl_hash_edges(const uint32_t* edges, uint64_t m, uint64_t index_base, 
  * into edges[0 .. 2 cap) with no host synchronisation; graph_offsets (device,
  * G + 1) receives the task offsets.  If a replay finds larger sizes than the
  * plan (changed inputs) it writes nothing and cl_plan_info reports 0 edges.
+ * A workspace that holds no counted plan (none, a failed one, or one of
+ * cl_plan) gives CL_ERR_NOT_PLANNED and nothing is captured.
  * ------------------------------------------------------------------------- */
 cl_status cl_batch_capture(const cl_graph* g /* host */, uint32_t G, const cl_tuning* t, void* ws,
                            uint32_t* edges, uint64_t cap, uint64_t* graph_offsets,

@@ -85,9 +85,6 @@ def lib():
                                ctypes.c_uint64, ctypes.c_double, _u32p, ctypes.c_uint64, _u64p, _u64p,
                                ctypes.c_int]
     L.orc_generate.restype = ctypes.c_int64
-    L.orc_node_counts.argtypes = [_f64p, ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
-                                  ctypes.c_uint64, ctypes.c_double, _u64p, ctypes.c_int]
-    L.orc_node_counts.restype = ctypes.c_int
     L.orc_partition.argtypes = [_f64p, ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64, _u64p, _u64p]
     L.orc_partition.restype = ctypes.c_int
     L.orc_costs.argtypes = [_f64p, ctypes.c_uint64, ctypes.c_double, _u64p]
@@ -251,18 +248,6 @@ def generate(w, S, seed, u_begin=0, u_end=None, e_seg=E_SEG, want_edges=True, nt
         raise OracleError(m2)
     assert m2 == m
     return edges[: int(m)], int(m), int(h.value), int(nc.value)
-
-
-def node_counts(w, S, seed, u_begin=0, u_end=None, e_seg=E_SEG, nthreads=0):
-    w, wp = _f64(w)
-    if u_end is None:
-        u_end = w.size
-    out = np.zeros(max(u_end - u_begin, 1), dtype=np.uint64)
-    st = lib().orc_node_counts(wp, w.size, float(S), int(seed), int(u_begin), int(u_end), float(e_seg),
-                               out.ctypes.data_as(_u64p), int(nthreads))
-    if st != 0:
-        raise OracleError(st)
-    return out[: u_end - u_begin]
 
 
 def graph_codes(w, S, seed0, nseeds, e_seg=E_SEG):

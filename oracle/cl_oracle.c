@@ -412,44 +412,15 @@ int64_t orc_generate(const double* w, uint64_t n, double S, uint64_t seed,
     return (int64_t)m;
 }
 
-/* per-source edge counts for [u_begin, u_end) (degree tests) */
-int orc_node_counts(const double* w, uint64_t n, double S, uint64_t seed,
-                    uint64_t u_begin, uint64_t u_end, double e_seg, uint64_t* counts, int nthreads)
-{
-    int st = orc_validate(w, n, S);
-    if (st != ORC_OK) return st;
-    if (u_begin > u_end || u_end > n) return ORC_ERR_INVALID_ARG;
-    double qscale = orc_qscale(w, n);
-    uint64_t* Q = (uint64_t*)malloc((size_t)(n + 1) * sizeof(uint64_t));
-    if (!Q) return ORC_ERR_INVALID_ARG;
-    orc_qscan(w, n, qscale, Q);
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#else
-    (void)nthreads;
-#endif
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t r = 0; r < (int64_t)(u_end - u_begin); ++r)
-        counts[r] = orc_node(w, n, S, seed, Q, qscale, e_seg, u_begin + (uint64_t)r, NULL, 0, NULL, NULL);
-    free(Q);
-    return ORC_OK;
-}
-
 /* ------------------------------------------------------------------------ */
-/* Alg. 2, Uniform Consecutive Partition, with P virtual processors.        */
+/* Uniform consecutive partition (Sec. 4), computed from its definition.    */
 /* Costs are Eq. 2, c_u = e_u + 1, with e_u from Eq. 6 taken on the exact    */
-/* quantised mass and kept in fixed point (units of 1/256 edge) so that the  */
-/* cumulative cost C_u is exact and every processor agrees on it:            */
+/* quantised mass and kept in fixed point (units of 1/256 edge), so that the */
+/* cumulative cost C_u = c_0 + ... + c_u is an exact integer:                */
 /*     c_u = floor(256 e_u) + 256,   e_u = (w_u/S) (Q_n - sigma_u - q_u)/QSCALE */
-/* Calc-Cost: block partial sums s_i of q, exclusive prefix S_i (= sigma at  */
-/* the block start), local recurrence for sigma_u and C_u, block totals z_i, */
-/* exclusive prefix Z_i added to the block.  Blocks are                      */
-/* [floor(i n/P), floor((i+1) n/P)).                                          */
-/* Make-Partition: Z = sum z_i; n_k = argmin_u (C_u >= k Z/P) (Eq. 5),        */
-/* i.e. C_u * P >= k * Z exactly.  Find-Boundaries is the divide-and-conquer */
-/* over floor(C_u P / Z) of Alg. 2, extended to test the pair                 */
-/* (block start - 1, block start) and to give every index of a jump of the   */
-/* floor the same boundary.  n_0 = 0, n_P = n.                               */
+/* Eq. 5: n_i = the smallest u with C_u >= i Z/P, Z = C_{n-1}; with integers  */
+/* that is C_u * P >= i * Z (128-bit products).  n_0 = 0, n_P = n.  Alg. 2   */
+/* is the parallel way of finding the same bounds; this is the plain one.    */
 /* ------------------------------------------------------------------------ */
 static uint64_t cost_units(const double* w, uint64_t n, double S, const uint64_t* Q,
                            double qscale, uint64_t u, uint64_t sigma_q, uint64_t q_u)
@@ -465,35 +436,6 @@ static uint64_t cost_units(const double* w, uint64_t n, double S, const uint64_t
     return (uint64_t)floor(scaled) + 256u;
 }
 
-/* floor(C * P / Z) with exact 128-bit arithmetic */
-static uint64_t part_index(uint64_t C, uint64_t P, uint64_t Z)
-{
-    unsigned __int128 num = (unsigned __int128)C * P;
-    return (uint64_t)(num / Z);
-}
-
-typedef struct {
-    const uint64_t* C;     /* cumulative cost, absolute node index */
-    uint64_t P, Z, n;
-    uint64_t* bounds;      /* P+1 */
-} part_ctx;
-
-/* boundaries inside [s, e] given f(s-1) = fprev */
-static void find_boundaries(const part_ctx* cx, uint64_t s, uint64_t e, uint64_t fprev)
-{
-    uint64_t fe = part_index(cx->C[e], cx->P, cx->Z);
-    if (fprev == fe) return;                 /* no boundary in [s, e] */
-    if (s == e) {
-        for (uint64_t kk = fprev + 1; kk <= fe && kk <= cx->P - 1; ++kk)
-            cx->bounds[kk] = s;
-        return;
-    }
-    uint64_t mid = s + (e - s) / 2;
-    uint64_t fm = part_index(cx->C[mid], cx->P, cx->Z);
-    find_boundaries(cx, s, mid, fprev);
-    find_boundaries(cx, mid + 1, e, fm);
-}
-
 int orc_partition(const double* w, uint64_t n, double S, uint64_t P, uint64_t* bounds,
                   uint64_t* total_cost_out)
 {
@@ -507,54 +449,25 @@ int orc_partition(const double* w, uint64_t n, double S, uint64_t P, uint64_t* b
     double qscale = orc_qscale(w, n);
     uint64_t* Q = (uint64_t*)malloc((size_t)(n + 1) * sizeof(uint64_t));
     uint64_t* C = (uint64_t*)malloc((size_t)n * sizeof(uint64_t));
-    uint64_t* s_blk = (uint64_t*)calloc((size_t)P, sizeof(uint64_t));
-    uint64_t* z_blk = (uint64_t*)calloc((size_t)P, sizeof(uint64_t));
-    if (!Q || !C || !s_blk || !z_blk) { free(Q); free(C); free(s_blk); free(z_blk); return ORC_ERR_INVALID_ARG; }
+    if (!Q || !C) { free(Q); free(C); return ORC_ERR_INVALID_ARG; }
     orc_qscan(w, n, qscale, Q);
-    /* q_u recovered from the scan (the quantised weight of u) */
-#define QV(u) (Q[(u) + 1] - Q[(u)])
-    /* Calc-Cost step 1: s_i = sum of the block's quantised weights */
-    for (uint64_t i = 0; i < P; ++i) {
-        uint64_t lo = (i * n) / P, hi = ((i + 1) * n) / P;
-        for (uint64_t u = lo; u < hi; ++u) s_blk[i] += QV(u);
+    uint64_t acc = 0;
+    for (uint64_t u = 0; u < n; ++u) {             /* C_u, sigma_u = Q_u */
+        acc += cost_units(w, n, S, Q, qscale, u, Q[u], Q[u + 1] - Q[u]);
+        C[u] = acc;
     }
-    /* step 2: exclusive prefix S_i; step 3: local sigma_u, C_u; z_i */
-    uint64_t S_i = 0;
-    for (uint64_t i = 0; i < P; ++i) {
-        uint64_t lo = (i * n) / P, hi = ((i + 1) * n) / P;
-        uint64_t sigma = S_i, Cacc = 0;
-        for (uint64_t u = lo; u < hi; ++u) {
-            Cacc += cost_units(w, n, S, Q, qscale, u, sigma, QV(u));
-            C[u] = Cacc;
-            sigma += QV(u);
-        }
-        z_blk[i] = Cacc;
-        S_i += s_blk[i];
-    }
-    /* step 4-5: exclusive prefix Z_i of the z_i, added to the block */
-    uint64_t Z_i = 0;
-    for (uint64_t i = 0; i < P; ++i) {
-        uint64_t lo = (i * n) / P, hi = ((i + 1) * n) / P;
-        for (uint64_t u = lo; u < hi; ++u) C[u] += Z_i;
-        Z_i += z_blk[i];
-    }
-#undef QV
-    /* Make-Partition */
-    uint64_t Z = Z_i;                                  /* = sum_i z_i = m + n in cost units */
+    uint64_t Z = C[n - 1];
     if (total_cost_out) *total_cost_out = Z;
-    part_ctx cx = { C, P, Z, n, bounds };
-    for (uint64_t i = 0; i < P; ++i) {
-        uint64_t lo = (i * n) / P, hi = ((i + 1) * n) / P;
-        if (lo >= hi) continue;
-        uint64_t fprev = (lo == 0) ? 0 : part_index(C[lo - 1], P, Z);
-        find_boundaries(&cx, lo, hi - 1, fprev);
+    /* Eq. 5 for i = 1 .. P-1; C is non-decreasing, so the smallest u moves   */
+    /* forward with i and one sweep finds them all                           */
+    uint64_t u = 0;
+    for (uint64_t i = 1; i < P; ++i) {
+        unsigned __int128 target = (unsigned __int128)i * Z;
+        while (u < n - 1 && (unsigned __int128)C[u] * P < target) ++u;
+        bounds[i] = u;
     }
-    /* a boundary index never reached (all remaining cost in one node) keeps n */
-    /* only if no node reaches it; Eq. 5's argmin exists for every k < P since  */
-    /* C_{n-1} = Z >= k Z / P, so every entry 1..P-1 has been written.          */
-    bounds[0] = 0;
     bounds[P] = n;
-    free(Q); free(C); free(s_blk); free(z_blk);
+    free(Q); free(C);
     return ORC_OK;
 }
 

@@ -735,7 +735,8 @@ cl_status cl_batch_capture(const cl_graph* g, uint32_t G, const cl_tuning* t, vo
   WsHeader h{};
   CL_TRY(hipMemcpyAsync(&h, dhdr, sizeof(h), hipMemcpyDeviceToHost, s));
   CL_TRY(hipStreamSynchronize(s));
-  if (h.magic != kWsMagic || !h.planned) return CL_ERR_NOT_PLANNED;
+  // only a counted plan (cl_count, cl_sample): its sizes bound every replay
+  if (h.magic != kWsMagic || h.planned != 1 || h.mode == 2 || h.status) return CL_ERR_NOT_PLANNED;
   if (h.G != G) return CL_ERR_INVALID_ARG;
   const FixedLayout F = fixed_layout(g, G);
   if (F.total_q != h.total_q || F.total_r != h.total_r) return CL_ERR_INVALID_ARG;

@@ -207,18 +207,49 @@ def test_write_windows(planner, cg):
 def test_validation_errors_match_oracle(cg):
     bad = {
         "unsorted": (np.array([1.0, 2.0, 0.5]), None),
+        "unsorted tie then rise": (np.array([3.0, 2.0, 2.0, 2.5]), None),
         "negative": (np.array([2.0, 1.0, -0.5]), None),
+        "negative subnormal": (np.array([1.0, -5e-324]), None),
         "nonfinite": (np.array([np.inf, 1.0]), 5.0),
         "nan": (np.array([3.0, np.nan]), 5.0),
         "S below w0": (np.array([5.0, 1.0]), 4.0),
+        "tiny head": (np.array([2.0 ** -961, 2.0 ** -962]), 1.0),
+        "nan and negative": (np.array([1.0, np.nan, -1.0, 5.0]), None),
+        "unsorted and negative": (np.array([1.0, 2.0, -1.0]), None),
+        "unsorted and S below w0": (np.array([4.0, 5.0]), 1.0),
     }
     for name, (w, S) in bad.items():
         S = S if S is not None else 10.0
         oc = O.validate(w, S)
         assert oc != 0, name
-        with pytest.raises(cg.ClError) as ei:
-            cg.cl_count([cg.Task(_to_dev(w), S, 1)])
-        assert ei.value.code == oc, name
+        for planner in (cg.cl_count, cg.cl_sample):
+            with pytest.raises(cg.ClError) as ei:
+                planner([cg.Task(_to_dev(w), S, 1)])
+            assert ei.value.code == oc, name
+    # accepted by both: -0.0, S == w_0, the smallest allowed head
+    for w, S in ((np.array([1.0, -0.0]), 1.0), (np.array([5.0]), 5.0),
+                 (np.array([2.0 ** -960, 2.0 ** -961]), 1.0)):
+        assert O.validate(w, S) == 0
+        plan = cg.cl_count([cg.Task(_to_dev(w), S, 1)])
+        assert plan.m == [O.generate(w, S, 1)[1]]
+
+
+def test_capture_refuses_a_plan_without_counts(cg):
+    """cl_batch_capture needs a counted plan (cl_count, cl_sample): a
+    workspace planned by cl_plan, or never planned, is refused."""
+    import torch
+    w = W.config_small(n=2000)
+    S = O.exact_sum(w)
+    tasks = [cg.Task(_to_dev(w), S, 1)]
+    s = torch.cuda.Stream()
+    plan = cg.cl_plan(tasks)
+    with pytest.raises(cg.ClError) as ei:
+        cg.cl_batch_capture(plan, s)
+    assert ei.value.code == -9
+    plan.ws.zero_()
+    with pytest.raises(cg.ClError) as ei:
+        cg.cl_batch_capture(plan, s)
+    assert ei.value.code == -9
 
 
 def test_partition_matches_oracle(cg):
