@@ -3,10 +3,14 @@
 n = 1e9 weights (exponent 2.1, mean 500, cap sqrt(500 n)), S exact, the
 uniform consecutive partition into 64 parts (Eq. 5) equal to the oracle's,
 then part 0 (the heavy head, ~3.9e9 edges) generated in one pass and written
-out in 4 slabs.  Checked: partition bounds bit-exact; per-source edge lists
-bit-exact on sampled sources; sortedness / u < v / range across all slabs;
-digest identical between the one-pass and the count-then-replay paths."""
-import math
+out in 4 slabs.  Checked: partition bounds bit-exact; the part's edge count
+and position-keyed digest over all slabs equal the oracle's (stored in
+``tests/golden/share_part0.json`` by ``tests/golden/make_golden.py``, which
+calls only the oracle); per-source edge lists bit-exact on sampled sources;
+sortedness / u < v / range across all slabs; the count-then-replay path gives
+the same digest."""
+import json
+import os
 
 import numpy as np
 import pytest
@@ -31,8 +35,13 @@ def cg():
     return clgen
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "share_part0.json")
+
+
 def test_share_of_the_billion_node_graph(cg):
     import torch
+    with open(GOLDEN) as f:
+        gold = json.load(f)
     print("share: generating 1e9 weights", flush=True)
     w = W.config_share()
     n = w.size
@@ -40,13 +49,14 @@ def test_share_of_the_billion_node_graph(cg):
     wd = torch.from_numpy(w).to("cuda:0")
     S = cg.cl_weight_sum(wd)
     print("share: oracle exact sum", flush=True)
-    assert S == O.exact_sum(w)
+    assert S == O.exact_sum(w) == float.fromhex(gold["S"])
     P = 64
     bounds, Z = cg.cl_partition(wd, S, P)
     print("share: oracle partition", flush=True)
     ob, oZ = O.partition(w, S, P)
-    assert Z == oZ and bounds == [int(x) for x in ob]
+    assert Z == oZ == gold["Z"] and bounds == [int(x) for x in ob]
     u1 = bounds[1]
+    assert u1 == gold["u_end"]
     seed = 3
     # one pass into slots, then 4 slabs through one buffer
     plan = cg.cl_sample([cg.Task(wd, S, seed, 0, u1)])
@@ -57,6 +67,8 @@ def test_share_of_the_billion_node_graph(cg):
     # Theorem 2: the part's edge count is within 3/2 of its expectation; the
     # cost model puts ~Z/P into each part
     assert 0.5 * Z / P / 256 < m < 1.5 * Z / P / 256
+    assert m == gold["m"]
+    assert info["candidates"] == gold["candidates"]
     slab = (m + 3) // 4
     buf = torch.empty((slab + 8, 2), dtype=torch.int32, device="cuda:0")
     acc1 = torch.zeros(1, dtype=torch.int64, device="cuda:0")
@@ -87,6 +99,7 @@ def test_share_of_the_billion_node_graph(cg):
         want = O.node_edges(w, S, seed, src, Q=Q, qscale=qs)
         got = np.concatenate(found.get(src, [np.zeros(0, dtype=np.int64)])).astype(np.uint32)
         assert np.array_equal(got, want), src
+    assert cg.hash_value(acc1) == gold["digest"]
     del plan
     torch.cuda.empty_cache()
     # the count-then-replay path gives the same digest
