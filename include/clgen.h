@@ -13,7 +13,8 @@
  *   - `stream` is a hipStream_t (NULL = the null stream); work is enqueued on
  *     it; calls documented as "synchronises" wait for their own work;
  *   - the caller owns every buffer (weights, workspace, edges); the library
- *     never allocates device memory and keeps no state between calls;
+ *     never allocates device memory and keeps no state between calls (the
+ *     one exception: the fixed per-GPU array of cl_sample_into_noalloc);
  *   - errors are returned as negative cl_status values, never thrown.
  *
  * Output of the generator: uint32 pairs (u, v) with u < v, sorted by (u, v),
@@ -173,6 +174,34 @@ cl_status cl_sample_into(const cl_graph* g /* host, G entries */, uint32_t G, co
                          void* ws, uint64_t ws_bytes, uint32_t* edges, uint64_t cap,
                          uint64_t* graph_offsets, uint64_t* m_out /* host */,
                          uint64_t* ws_required /* host, may be NULL */, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * cl_sample_into with the workspace taken from a fixed array of
+ * CL_NOALLOC_SCRATCH_BYTES in device memory that the library holds, one
+ * copy per GPU, from the loading of the library until the process ends.
+ * The caller passes only inputs and outputs (g, edges, graph_offsets); the
+ * call allocates no device memory (no hipMalloc / hipFree, no allocating
+ * library routine).  Arguments, outputs and synchronisation as for
+ * cl_sample_into; when m exceeds cap, m_out is set, edges holds the first cap
+ * edges and the call returns CL_ERR_CAPACITY (call again with a larger
+ * buffer: the array's plan is not reachable through cl_generate).
+ * Limit: a plan whose workspace would exceed CL_NOALLOC_SCRATCH_BYTES (about
+ * 32 bytes per source plus 9 to 10 bytes per edge: a power-law graph of
+ * n = 1e5 with 2.7e6 edges needs 26.5 MB, so graphs up to about 6e6 edges
+ * fit) returns CL_ERR_WORKSPACE, with the bytes it would need in
+ * ws_required, before any edge is generated; edges are then untouched.
+ * Every call on one GPU uses that GPU's one array and leaves its contents
+ * behind (each call starts by resetting what must start at zero): calls
+ * that overlap on one GPU (concurrent streams or host threads) race and
+ * give undefined results; serialise them.
+ * ------------------------------------------------------------------------- */
+#define CL_NOALLOC_SCRATCH_BYTES (64ull << 20)
+cl_status cl_sample_into_noalloc(const cl_graph* g /* host, G entries */, uint32_t G, const cl_tuning* t,
+                                 uint32_t* edges, uint64_t cap, uint64_t* graph_offsets,
+                                 uint64_t* m_out /* host */, uint64_t* ws_required /* host, may be NULL */,
+                                 void* stream);
 
 /* ---------------------------------------------------------------------------
  * Generation, write pass: the output E of Create-Edges (Sec. 3, Alg. 1) for

@@ -74,6 +74,8 @@ def lib():
                                _U64, _P, _U64P, _U64P, _P]),
         "cl_count": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _U64, _U64P,
                          _U64P, _P]),
+        "cl_sample_into_noalloc": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P,
+                                       _U64, _P, _U64P, _U64P, _P]),
         "cl_generate": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _U64, _P, _P]),
         "cl_plan_info": (S, [_P, _U64P, _U64P, _U64P, _U64P, ctypes.POINTER(ctypes.c_float),
                               ctypes.POINTER(ctypes.c_uint32), _U64P, _P]),
@@ -289,6 +291,31 @@ def cl_sample_into(tasks: Sequence[Task], edges: torch.Tensor, cap: Optional[int
     plan = _plan("cl_sample_into", 1, tasks, tuning, ws, stream, into=(edges, cap, graph_offsets),
                  ws_growth=ws_growth)
     return plan, "over_capacity" not in plan.keep
+
+
+def cl_sample_into_noalloc(tasks: Sequence[Task], edges: torch.Tensor, cap: Optional[int] = None,
+                           graph_offsets: Optional[torch.Tensor] = None, tuning: Optional[dict] = None,
+                           stream=None):
+    """cl_sample_into with the library's fixed device array as the workspace
+    (no device allocation in the call).  Returns (m per task, fits,
+    workspace bytes the plan needed).  Raises ClError(CL_ERR_WORKSPACE) when
+    the plan would need more than the array holds."""
+    L = lib()
+    tasks = list(tasks)
+    arr = _graph_array(tasks)
+    if cap is None:
+        cap = edges.numel() // 2
+    assert edges.dtype == torch.int32 and edges.is_contiguous() and edges.numel() >= 2 * cap
+    m = (ctypes.c_uint64 * len(tasks))()
+    req = _U64(0)
+    code = L.cl_sample_into_noalloc(arr, len(tasks), _tuning(tuning), _ptr(edges), int(cap), _ptr(graph_offsets), m,
+                                    ctypes.byref(req), _stream(stream))
+    if code != -7:
+        _check(code, "cl_sample_into_noalloc")
+    return [int(x) for x in m], code == CL_OK, int(req.value)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # CL_NOALLOC_SCRATCH_BYTES
 
 
 def cl_plan(tasks: Sequence[Task], tuning: Optional[dict] = None, ws: Optional[torch.Tensor] = None,

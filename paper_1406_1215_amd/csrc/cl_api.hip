@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -630,6 +631,57 @@ cl_status cl_sample_into(const cl_graph* g, uint32_t G, const cl_tuning* t, void
   if (cap > 0 && !edges) return CL_ERR_INVALID_ARG;
   const IntoOut into{edges, cap, graph_offsets};
   return plan_common(g, G, t, ws, ws_bytes, m_out, ws_required, stream, 1u, &into);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ no-allocation variant
+// The workspace of cl_sample_into_noalloc: a fixed array in device memory,
+// one copy per GPU (allocated when the code object is loaded, held until the
+// process ends).  Host code never passes `scratch` itself to a kernel or a
+// copy (on the host the name is only a stand-in for the symbol): it uses the
+// device address that hipGetSymbolAddress returns for the current GPU.
+static __device__ __align__(256) unsigned char scratch[CL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of the current GPU's scratch array, looked up once per
+// device (with that device current) and kept
+cl_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return CL_ERR_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return CL_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CL_OK;
+}
+}  // namespace
+
+extern "C" {
+
+cl_status cl_sample_into_noalloc(const cl_graph* g, uint32_t G, const cl_tuning* t, uint32_t* edges, uint64_t cap,
+                                 uint64_t* graph_offsets, uint64_t* m_out, uint64_t* ws_required, void* stream) {
+  if (cap > 0 && !edges) return CL_ERR_INVALID_ARG;
+  void* ws = nullptr;
+  const cl_status st = scratch_of_current_device(&ws);
+  if (st != CL_OK) return st;
+  // a plan that needs more than the array fails with CL_ERR_WORKSPACE before
+  // its sizes are laid out (ws_required reports what it would need)
+  const IntoOut into{edges, cap, graph_offsets};
+  return plan_common(g, G, t, ws, CL_NOALLOC_SCRATCH_BYTES, m_out, ws_required, stream, 1u, &into);
 }
 
 cl_status cl_plan(const cl_graph* g, uint32_t G, const cl_tuning* t, void* ws, uint64_t ws_bytes,
