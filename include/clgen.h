@@ -86,6 +86,10 @@ typedef struct cl_tuning {
                               lanes still busy when the work runs out finish close together
                               (graphs of at least 4096 units; in a batch only the last task, since
                               the queue hands out the tasks' units in order); 1 = uniform units */
+  uint32_t ed_rows;        /* expected-degree tiles: rows per thread, 1, 2 (default) or 4 */
+  uint32_t ed_cols;        /* expected-degree tiles: columns per tile, 512, 1024 (default) or 2048;
+                              other values of either: CL_ERR_INVALID_ARG.  The tile shape changes
+                              only the float32 summation order inside a tile */
 } cl_tuning;
 
 /* ---------------------------------------------------------------------------
@@ -266,6 +270,32 @@ cl_status cl_plan(const cl_graph* g /* host, G entries */, uint32_t G, const cl_
  * ------------------------------------------------------------------------- */
 cl_status cl_degrees(void* ws, const cl_tuning* t, uint32_t* deg, uint64_t deg_len, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Work-unit statistics of a plan, for Sec. 4's comparison of partitions
+ * (runtime of a part against its cost c(V_i) = m_i + |V_i|, Eq. 2-4; the
+ * imbalance of the naive consecutive and the round-robin partitions): runs
+ * the planned lanes once more as a count pass (the same candidates; no
+ * output; the plan's counts are rewritten with the same values) and records
+ * for every work unit i four 64-bit words at stats[4 i]:
+ *   [0] wave clock (s_memrealtime, 100 MHz) when a lane took the unit,
+ *   [1] wave clock when it finished it,
+ *   [2] low 32 bits: the unit's plan cost (the sum over its segments of
+ *       c_u / K_u, in cost units of 1/16 expected candidate, rounded);
+ *       high 32 bits: the candidates it visited,
+ *   [3] low 32 bits: its edges; high 32 bits: the lane that ran it
+ *       (wavefront index * 64 + lane).
+ * Every unit gets a record; the units of the padding to whole wavefronts
+ * carry no segments (cost, candidates and edges 0).
+ * ws: a plan of cl_count, cl_sample or cl_plan (any partition policy).
+ * stats: device, stats_len >= 4 x units (units_out, host, may be NULL, gets
+ * the number of units), else CL_ERR_CAPACITY with nothing launched (stats
+ * may be NULL with stats_len 0 to ask for the size).  Synchronises once (reads the
+ * plan's sizes), then launches asynchronously.  A project addition for
+ * measurement; it does not change any output.
+ * ------------------------------------------------------------------------- */
+cl_status cl_unit_stats(void* ws, const cl_tuning* t, uint64_t* stats, uint64_t stats_len,
+                        uint64_t* units_out /* host, may be NULL */, void* stream);
+
 /* Totals of the plan in ws (host outputs, each may be NULL; synchronises).
  * lanes includes the padding to whole wavefronts; candidates is the number of
  * candidates the lane kernel visited (the edge-plus-source work of Eq. 2-4,
@@ -316,7 +346,7 @@ cl_status cl_batch_destroy(void* graph_exec);
  * ------------------------------------------------------------------------- */
 cl_status cl_expected_degree_workspace(uint64_t n, uint64_t* bytes_out /* host */);
 cl_status cl_expected_degree(const float* w, uint64_t n, double S, double* d_out, void* ws, uint64_t ws_bytes,
-                             void* stream);
+                             const cl_tuning* t /* tile shape; NULL = defaults */, void* stream);
 
 /* Adjoint of cl_expected_degree: given g = dL/dd (float64), writes
  *   grad_w[k] = (g_k A_k + B_k - T) / S,  A_k = sum_{j != k, x_kj < 1} w_j,
@@ -326,7 +356,7 @@ cl_status cl_expected_degree(const float* w, uint64_t n, double S, double* d_out
  * Asynchronous. */
 cl_status cl_expected_degree_backward(const float* w, uint64_t n, double S, const double* grad_d,
                                       int s_depends_on_w, float* grad_w, void* ws, uint64_t ws_bytes,
-                                      void* stream);
+                                      const cl_tuning* t /* tile shape; NULL = defaults */, void* stream);
 
 /* Number of compute units of the current device (host; 0 on error). */
 uint32_t cl_device_cus(void);

@@ -27,25 +27,28 @@ class ExpectedDegree(torch.autograd.Function):
     includes dS/dw_k = 1 (S is the sum of the same weights)."""
 
     @staticmethod
-    def forward(ctx, w: torch.Tensor, S: float, s_from_w: bool = True):
+    def forward(ctx, w: torch.Tensor, S: float, s_from_w: bool = True, tuning: Optional[dict] = None):
         w = w.contiguous()
-        d = clgen.cl_expected_degree(w, S)
+        d = clgen.cl_expected_degree(w, S, tuning=tuning)
         ctx.save_for_backward(w)
         ctx.S = S
         ctx.s_from_w = s_from_w
+        ctx.tuning = tuning
         return d
 
     @staticmethod
     def backward(ctx, g: torch.Tensor):
         (w,) = ctx.saved_tensors
-        grad = clgen.cl_expected_degree_backward(w, ctx.S, g.to(torch.float64).contiguous(), ctx.s_from_w)
-        return grad, None, None
+        grad = clgen.cl_expected_degree_backward(w, ctx.S, g.to(torch.float64).contiguous(), ctx.s_from_w,
+                                                 tuning=ctx.tuning)
+        return grad, None, None, None
 
 
-def expected_degree(w: torch.Tensor) -> torch.Tensor:
-    """Expected degrees of float32 weights with S = sum(w), differentiable."""
+def expected_degree(w: torch.Tensor, tuning: Optional[dict] = None) -> torch.Tensor:
+    """Expected degrees of float32 weights with S = sum(w), differentiable;
+    tuning: the kernels' tile shape (ed_rows, ed_cols), defaults if None."""
     S = float(w.detach().to(torch.float64).sum())
-    return ExpectedDegree.apply(w, S, True)
+    return ExpectedDegree.apply(w, S, True, tuning)
 
 
 @dataclass
@@ -59,10 +62,16 @@ class CalibrationResult:
 
 
 def calibrate(t: torch.Tensor, steps: int = 200, lr: float = 0.05, betas=(0.9, 0.999), eps: float = 1e-8,
-              log_every: int = 0, w0: Optional[torch.Tensor] = None) -> CalibrationResult:
-    """Adam on log w so that the expected degrees match the targets t."""
+              log_every: int = 0, w0: Optional[torch.Tensor] = None,
+              tuning: Optional[dict] = None) -> CalibrationResult:
+    """Adam on log w so that the expected degrees match the targets t.  The
+    kernels' tile shape is `tuning`, else the autotuner's cached choice for
+    n^2 pairs, else the defaults."""
     import time
+    from . import autotune
     dev = t.device
+    if tuning is None:
+        tuning = autotune.lookup(float(t.numel()) ** 2, kind="expdeg")
     t64 = t.to(torch.float64)
     init = (w0 if w0 is not None else t).to(torch.float32).clamp_min(1e-30)
     theta = torch.nn.Parameter(torch.log(init).clone())
@@ -74,7 +83,7 @@ def calibrate(t: torch.Tensor, steps: int = 200, lr: float = 0.05, betas=(0.9, 0
     for it in range(steps):
         opt.zero_grad(set_to_none=True)
         w = torch.exp(theta)
-        d = expected_degree(w)
+        d = expected_degree(w, tuning)
         loss = torch.mean((d / t64 - 1.0) ** 2)
         loss.backward()
         opt.step()
@@ -84,7 +93,7 @@ def calibrate(t: torch.Tensor, steps: int = 200, lr: float = 0.05, betas=(0.9, 0
     secs = time.perf_counter() - t0
     with torch.no_grad():
         w = torch.exp(theta).to(torch.float32)
-        d = expected_degree(w)
+        d = expected_degree(w, tuning)
         rel = (d / t64 - 1.0).abs()
         final = float(torch.mean((d / t64 - 1.0) ** 2))
         w64 = torch.sort(w.to(torch.float64), descending=True).values.contiguous()

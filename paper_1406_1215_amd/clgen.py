@@ -39,7 +39,8 @@ class cl_graph(ctypes.Structure):
 
 class cl_tuning(ctypes.Structure):
     _fields_ = [("lane_budget", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
-                ("slot_margin", ctypes.c_uint32), ("partition", ctypes.c_uint32), ("tail_units", ctypes.c_uint32)]
+                ("slot_margin", ctypes.c_uint32), ("partition", ctypes.c_uint32), ("tail_units", ctypes.c_uint32),
+                ("ed_rows", ctypes.c_uint32), ("ed_cols", ctypes.c_uint32)]
 
 
 _lib = None
@@ -82,6 +83,7 @@ def lib():
         "cl_hash_edges": (S, [_P, _U64, _U64, _P, _P]),
         "cl_degrees": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _P]),
         "cl_generate_csr": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _P, _U64, _P]),
+        "cl_unit_stats": (S, [_P, ctypes.POINTER(cl_tuning), _P, _U64, _U64P, _P]),
         "cl_plan": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _U64, _U64P,
                         _P]),
         "cl_batch_capture": (S, [ctypes.POINTER(cl_graph), ctypes.c_uint32, ctypes.POINTER(cl_tuning), _P, _P, _U64,
@@ -89,8 +91,9 @@ def lib():
         "cl_batch_launch": (S, [_P, _P]),
         "cl_batch_destroy": (S, [_P]),
         "cl_expected_degree_workspace": (S, [_U64, _U64P]),
-        "cl_expected_degree": (S, [_P, _U64, ctypes.c_double, _P, _P, _U64, _P]),
-        "cl_expected_degree_backward": (S, [_P, _U64, ctypes.c_double, _P, ctypes.c_int, _P, _P, _U64, _P]),
+        "cl_expected_degree": (S, [_P, _U64, ctypes.c_double, _P, _P, _U64, ctypes.POINTER(cl_tuning), _P]),
+        "cl_expected_degree_backward": (S, [_P, _U64, ctypes.c_double, _P, ctypes.c_int, _P, _P, _U64,
+                                            ctypes.POINTER(cl_tuning), _P]),
         "cl_device_cus": (ctypes.c_uint32, []),
         "cl_version": (ctypes.c_char_p, []),
     }
@@ -126,7 +129,8 @@ def _tuning(t: Optional[dict]):
         return None
     return ctypes.pointer(cl_tuning(int(t.get("lane_budget", 0)), int(t.get("blocks_per_cu", 0)),
                                     int(t.get("slot_margin", 0)), int(t.get("partition", 0)),
-                                    int(t.get("tail_units", 0))))
+                                    int(t.get("tail_units", 0)), int(t.get("ed_rows", 0)),
+                                    int(t.get("ed_cols", 0))))
 
 
 def _f64(w: torch.Tensor) -> torch.Tensor:
@@ -383,6 +387,29 @@ def cl_degrees(plan: Plan, deg: Optional[torch.Tensor] = None, stream=None) -> L
     return out
 
 
+def cl_unit_stats(plan: Plan, tuning: Optional[dict] = None, stream=None) -> dict:
+    """Per-unit records of a statistics pass over the plan (see clgen.h):
+    numpy arrays t0, t1 (wave clock, 100 MHz ticks), cost (cost units of
+    1/16 expected candidate), visits, edges and lane, one entry per unit
+    (padding units included)."""
+    import numpy as np
+    L = lib()
+    units = _U64(0)
+    code = L.cl_unit_stats(_ptr(plan.ws), _tuning(tuning if tuning is not None else plan.tuning), None, 0,
+                           ctypes.byref(units), _stream(stream))
+    if code != -7 and code != CL_OK:
+        _check(code, "cl_unit_stats")
+    n = int(units.value)
+    buf = torch.zeros(4 * max(n, 1), dtype=torch.int64, device=plan.ws.device)
+    _check(L.cl_unit_stats(_ptr(plan.ws), _tuning(tuning if tuning is not None else plan.tuning), _ptr(buf),
+                           buf.numel(), None, _stream(stream)), "cl_unit_stats")
+    a = buf.cpu().numpy().view(np.uint64).reshape(-1, 4)[:n]
+    w2 = a[:, 2]
+    w3 = a[:, 3]
+    return {"t0": a[:, 0], "t1": a[:, 1], "cost": (w2 & 0xFFFFFFFF), "visits": (w2 >> np.uint64(32)),
+            "edges": (w3 & 0xFFFFFFFF), "lane": (w3 >> np.uint64(32))}
+
+
 def cl_plan_info(plan_or_ws, stream=None) -> dict:
     L = lib()
     ws = plan_or_ws.ws if isinstance(plan_or_ws, Plan) else plan_or_ws
@@ -460,20 +487,23 @@ def _ed_ws(n: int, device) -> torch.Tensor:
     return _ws(need.value, device)
 
 
-def cl_expected_degree(w32: torch.Tensor, S: float, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """d_i = sum_{j != i} min(w_i w_j / S, 1) (float32 tiles, float64 rows)."""
+def cl_expected_degree(w32: torch.Tensor, S: float, ws: Optional[torch.Tensor] = None, stream=None,
+                       tuning: Optional[dict] = None) -> torch.Tensor:
+    """d_i = sum_{j != i} min(w_i w_j / S, 1) (float32 tiles, float64 rows);
+    tuning may give the tile shape (ed_rows, ed_cols)."""
     assert w32.dtype == torch.float32 and w32.is_contiguous()
     n = w32.numel()
     if ws is None:
         ws = _ed_ws(n, w32.device)
     d = torch.empty(n, dtype=torch.float64, device=w32.device)
-    _check(lib().cl_expected_degree(_ptr(w32), n, float(S), _ptr(d), _ptr(ws), ws.numel(), _stream(stream)),
-           "cl_expected_degree")
+    _check(lib().cl_expected_degree(_ptr(w32), n, float(S), _ptr(d), _ptr(ws), ws.numel(), _tuning(tuning),
+                                    _stream(stream)), "cl_expected_degree")
     return d
 
 
 def cl_expected_degree_backward(w32: torch.Tensor, S: float, grad_d: torch.Tensor, s_depends_on_w: bool = True,
-                                ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+                                ws: Optional[torch.Tensor] = None, stream=None,
+                                tuning: Optional[dict] = None) -> torch.Tensor:
     assert w32.dtype == torch.float32 and grad_d.dtype == torch.float64
     n = w32.numel()
     if ws is None:
@@ -481,7 +511,7 @@ def cl_expected_degree_backward(w32: torch.Tensor, S: float, grad_d: torch.Tenso
     g = torch.empty(n, dtype=torch.float32, device=w32.device)
     _check(lib().cl_expected_degree_backward(_ptr(w32), n, float(S), _ptr(grad_d.contiguous()),
                                              1 if s_depends_on_w else 0, _ptr(g), _ptr(ws), ws.numel(),
-                                             _stream(stream)), "cl_expected_degree_backward")
+                                             _tuning(tuning), _stream(stream)), "cl_expected_degree_backward")
     return g
 
 

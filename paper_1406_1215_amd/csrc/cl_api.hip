@@ -28,6 +28,7 @@ constexpr uint32_t kDefaultBudget = 192;
 constexpr uint32_t kDefaultBlocksPerCu = 3;
 constexpr int kPersistThreads = 256;
 unsigned long long* const kNoRows = nullptr;   // row counts: CSR output only
+UnitStat* const kNoStats = nullptr;            // unit records: statistics pass only
 static_assert(kPersistThreads == kLaneThreads, "the lane kernels stage output for 256 threads");
 
 inline uint64_t align_up(uint64_t x, uint64_t a = kAlign) { return (x + a - 1) / a * a; }
@@ -216,12 +217,12 @@ hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* 
     if (e != hipSuccess) return e;
     if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL((k_lanes<2>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                       static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr), kNoRows);
+                       static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr), kNoRows, kNoStats);
     if (ev1) (void)hipEventRecord(ev1, s);
   } else {
     if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL((k_lanes<0>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                       static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr), kNoRows);
+                       static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr), kNoRows, kNoStats);
     if (ev1) (void)hipEventRecord(ev1, s);
   }
   hipError_t e = device_scan<uint64_t>(CntIn{{}, h.lane_cnt, h.cap_nl}, OffOut{{}, h.lane_pos}, h.cap_nl + 1,
@@ -241,7 +242,7 @@ hipError_t launch_write(WsHeader* dhdr, const cl_tuning* t, uint32_t* edges, uin
   hipLaunchKernelGGL((k_compact<false>), dim3(cus * 16), dim3(256), 0, s, dhdr, reinterpret_cast<uint2*>(edges), lo,
                      hi, kNoRows);   // also clears the unit queue
   hipLaunchKernelGGL((k_lanes<1>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                     reinterpret_cast<uint2*>(edges), lo, hi, static_cast<uint32_t*>(nullptr), kNoRows);
+                     reinterpret_cast<uint2*>(edges), lo, hi, static_cast<uint32_t*>(nullptr), kNoRows, kNoStats);
   if (graph_offsets) hipLaunchKernelGGL(k_graph_offsets, dim3(16), dim3(256), 0, s, dhdr, graph_offsets);
   return hipGetLastError();
 }
@@ -715,7 +716,29 @@ cl_status cl_degrees(void* ws, const cl_tuning* t, uint32_t* deg, uint64_t deg_l
   if (deg_len < back.total_q) return CL_ERR_CAPACITY;
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
   hipLaunchKernelGGL((k_lanes<3>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                     static_cast<uint2*>(nullptr), 0ull, 0ull, deg, kNoRows);
+                     static_cast<uint2*>(nullptr), 0ull, 0ull, deg, kNoRows, kNoStats);
+  return hip_status(hipGetLastError());
+}
+
+cl_status cl_unit_stats(void* ws, const cl_tuning* t, uint64_t* stats, uint64_t stats_len, uint64_t* units_out,
+                        void* stream) {
+  if (!ws || (!stats && stats_len > 0)) return CL_ERR_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  WsHeader* dhdr = static_cast<WsHeader*>(ws);
+  WsHeader back{};
+  CL_TRY(hipMemcpyAsync(&back, ws, sizeof(back), hipMemcpyDeviceToHost, s));
+  CL_TRY(hipStreamSynchronize(s));
+  if (back.magic != kWsMagic) return CL_ERR_NOT_PLANNED;
+  if (back.status) return status_error(back.status);
+  if (!back.planned) return CL_ERR_NOT_PLANNED;
+  if (units_out) *units_out = back.total_nl;
+  if (stats_len < 4 * back.total_nl) return CL_ERR_CAPACITY;
+  hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(4 * back.total_nl, 256, stream_grid_cap())), dim3(256), 0, s,
+                     reinterpret_cast<unsigned long long*>(stats), 4 * back.total_nl);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, &dhdr->queue, 0u);
+  hipLaunchKernelGGL((k_lanes<0, true>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
+                     static_cast<uint2*>(nullptr), 0ull, 0ull, static_cast<uint32_t*>(nullptr), kNoRows,
+                     reinterpret_cast<UnitStat*>(stats));
   return hip_status(hipGetLastError());
 }
 
@@ -740,7 +763,7 @@ cl_status cl_generate_csr(void* ws, const cl_tuning* t, uint32_t* col, uint64_t 
   hipLaunchKernelGGL((k_compact<true>), dim3(cus * 16), dim3(256), 0, s, dhdr, reinterpret_cast<uint2*>(col), 0ull,
                      cap, rows);   // also clears the unit queue
   hipLaunchKernelGGL((k_lanes<4>), dim3(persistent_grid(t)), dim3(kPersistThreads), 0, s, dhdr,
-                     reinterpret_cast<uint2*>(col), 0ull, cap, static_cast<uint32_t*>(nullptr), rows);
+                     reinterpret_cast<uint2*>(col), 0ull, cap, static_cast<uint32_t*>(nullptr), rows, kNoStats);
   CL_TRY(hipGetLastError());
   CL_TRY(device_scan<uint64_t>(RowIn{{}, rows, back.total_q}, RowOut{{}, rows}, back.total_q, back.scan_tmp, s));
   return CL_OK;
@@ -823,25 +846,37 @@ cl_status cl_batch_destroy(void* graph_exec) {
 // ------------------------------------------------------- expected degree
 cl_status cl_expected_degree_workspace(uint64_t n, uint64_t* bytes_out) {
   if (!bytes_out) return CL_ERR_INVALID_ARG;
-  const uint64_t nt = (n + kEdCols - 1) / kEdCols;
+  const uint64_t nt = (n + kEdColsMin - 1) / kEdColsMin;
   const uint64_t nb = (n + 255) / 256;
-  // a, thresholds, gw (float n each), two float partial planes, A, B (double n), T partials
+  // a, thresholds, gw (float n each), two float partial planes (for the
+  // narrowest tiles), A, B (double n), T partials
   *bytes_out = 3 * align_up(4 * (n + 1)) + 2 * align_up(4 * nt * n + 4) + 2 * align_up(8 * (n + 1)) +
                align_up(8 * (nb + 1)) + align_up(8);
   return CL_OK;
 }
 
+}  // extern "C"
+
 namespace {
 struct EdLayout {
   float *a, *thr, *gw, *pA, *pB;
   double *A, *B, *tp, *T;
-  uint32_t nt, nb;
+  uint32_t nt, nb, nrow;
+  int R, C;
 };
 
-EdLayout ed_layout(void* ws, uint64_t n) {
+// tile shape of the expected-degree kernels from the tuning (rows per lane,
+// columns per tile); false for a shape that has no instantiation
+bool ed_shape(const cl_tuning* t, int* R, int* C) {
+  *R = (t && t->ed_rows) ? static_cast<int>(t->ed_rows) : kEdRowsDefault;
+  *C = (t && t->ed_cols) ? static_cast<int>(t->ed_cols) : kEdColsDefault;
+  return (*R == 1 || *R == 2 || *R == 4) && (*C == 512 || *C == 1024 || *C == 2048);
+}
+
+EdLayout ed_layout(void* ws, uint64_t n, int R, int C) {
   EdLayout L{};
   char* base = static_cast<char*>(ws);
-  const uint64_t nt = (n + kEdCols - 1) / kEdCols;
+  const uint64_t ntmax = (n + kEdColsMin - 1) / kEdColsMin;
   const uint64_t nb = (n + 255) / 256;
   uint64_t off = 0;
   L.a = reinterpret_cast<float*>(base + off);
@@ -851,9 +886,9 @@ EdLayout ed_layout(void* ws, uint64_t n) {
   L.gw = reinterpret_cast<float*>(base + off);
   off += align_up(4 * (n + 1));
   L.pA = reinterpret_cast<float*>(base + off);
-  off += align_up(4 * nt * n + 4);
+  off += align_up(4 * ntmax * n + 4);
   L.pB = reinterpret_cast<float*>(base + off);
-  off += align_up(4 * nt * n + 4);
+  off += align_up(4 * ntmax * n + 4);
   L.A = reinterpret_cast<double*>(base + off);
   off += align_up(8 * (n + 1));
   L.B = reinterpret_cast<double*>(base + off);
@@ -861,44 +896,73 @@ EdLayout ed_layout(void* ws, uint64_t n) {
   L.tp = reinterpret_cast<double*>(base + off);
   off += align_up(8 * (nb + 1));
   L.T = reinterpret_cast<double*>(base + off);
-  L.nt = static_cast<uint32_t>(nt);
+  L.nt = static_cast<uint32_t>((n + C - 1) / C);
   L.nb = static_cast<uint32_t>(nb);
+  L.nrow = static_cast<uint32_t>((n + static_cast<uint64_t>(kEdLanes) * R - 1) / (static_cast<uint64_t>(kEdLanes) * R));
+  L.R = R;
+  L.C = C;
   return L;
+}
+
+template <int R, int C>
+void launch_ed_tiles(bool backward, const EdLayout& L, const float* w, uint64_t n, hipStream_t s) {
+  const dim3 grid(L.nrow, L.nt);
+  if (backward)
+    hipLaunchKernelGGL((k_expdeg_bwd_tile<R, C>), grid, dim3(kEdLanes), 0, s, w, L.thr, L.gw, n, L.pA, L.pB);
+  else
+    hipLaunchKernelGGL((k_expdeg_tile<R, C>), grid, dim3(kEdLanes), 0, s, w, L.a, n, L.pA);
+}
+
+template <int R>
+void launch_ed_tiles_r(bool backward, const EdLayout& L, const float* w, uint64_t n, hipStream_t s) {
+  if (L.C == 512) launch_ed_tiles<R, 512>(backward, L, w, n, s);
+  else if (L.C == 1024) launch_ed_tiles<R, 1024>(backward, L, w, n, s);
+  else launch_ed_tiles<R, 2048>(backward, L, w, n, s);
+}
+
+void launch_ed(bool backward, const EdLayout& L, const float* w, uint64_t n, hipStream_t s) {
+  if (L.R == 1) launch_ed_tiles_r<1>(backward, L, w, n, s);
+  else if (L.R == 2) launch_ed_tiles_r<2>(backward, L, w, n, s);
+  else launch_ed_tiles_r<4>(backward, L, w, n, s);
 }
 }  // namespace
 
+extern "C" {
+
 cl_status cl_expected_degree(const float* w, uint64_t n, double S, double* d_out, void* ws, uint64_t ws_bytes,
-                             void* stream) {
+                             const cl_tuning* t, void* stream) {
   if ((n > 0 && (!w || !d_out)) || !finite_pos(S)) return CL_ERR_INVALID_ARG;
   if (n > (1ull << 31)) return CL_ERR_TOO_LARGE;
+  int R = 0, C = 0;
+  if (!ed_shape(t, &R, &C)) return CL_ERR_INVALID_ARG;
   uint64_t need = 0;
   cl_expected_degree_workspace(n, &need);
   if (!ws || ws_bytes < need) return CL_ERR_WORKSPACE;
   if (n == 0) return CL_OK;
   hipStream_t s = as_stream(stream);
-  const EdLayout L = ed_layout(ws, n);
-  const uint32_t nrow = static_cast<uint32_t>((n + kEdRows - 1) / kEdRows);
+  const EdLayout L = ed_layout(ws, n, R, C);
   hipLaunchKernelGGL(k_rowscale, dim3(L.nb), dim3(256), 0, s, w, n, S, L.a);
-  hipLaunchKernelGGL(k_expdeg_tile, dim3(nrow, L.nt), dim3(kEdLanes), 0, s, w, L.a, n, L.pA);
+  launch_ed(false, L, w, n, s);
   hipLaunchKernelGGL(k_expdeg_rows, dim3(L.nb), dim3(256), 0, s, w, L.a, n, L.nt, L.pA, d_out);
   return hip_status(hipGetLastError());
 }
 
 cl_status cl_expected_degree_backward(const float* w, uint64_t n, double S, const double* grad_d, int s_depends_on_w,
-                                      float* grad_w, void* ws, uint64_t ws_bytes, void* stream) {
+                                      float* grad_w, void* ws, uint64_t ws_bytes, const cl_tuning* t, void* stream) {
   if ((n > 0 && (!w || !grad_d || !grad_w)) || !finite_pos(S)) return CL_ERR_INVALID_ARG;
   if (n > (1ull << 31)) return CL_ERR_TOO_LARGE;
+  int R = 0, C = 0;
+  if (!ed_shape(t, &R, &C)) return CL_ERR_INVALID_ARG;
   uint64_t need = 0;
   cl_expected_degree_workspace(n, &need);
   if (!ws || ws_bytes < need) return CL_ERR_WORKSPACE;
   if (n == 0) return CL_OK;
   hipStream_t s = as_stream(stream);
-  const EdLayout L = ed_layout(ws, n);
-  const uint32_t nrow = static_cast<uint32_t>((n + kEdRows - 1) / kEdRows);
+  const EdLayout L = ed_layout(ws, n, R, C);
   hipLaunchKernelGGL(k_rowscale, dim3(L.nb), dim3(256), 0, s, w, n, S, L.a);
   hipLaunchKernelGGL(k_threshold, dim3(L.nb), dim3(256), 0, s, L.a, n, L.thr);
   hipLaunchKernelGGL(k_gw, dim3(L.nb), dim3(256), 0, s, w, grad_d, n, L.gw);
-  hipLaunchKernelGGL(k_expdeg_bwd_tile, dim3(nrow, L.nt), dim3(kEdLanes), 0, s, w, L.thr, L.gw, n, L.pA, L.pB);
+  launch_ed(true, L, w, n, s);
   hipLaunchKernelGGL(k_expdeg_bwd_rows, dim3(L.nb), dim3(256), 0, s, w, L.a, grad_d, L.gw, n, L.nt, L.pA, L.pB, L.A,
                      L.B, L.tp);
   hipLaunchKernelGGL(k_sum_dbl, dim3(1), dim3(256), 0, s, L.tp, L.nb, L.T);

@@ -3,8 +3,8 @@
 //   d_i = sum_{j != i} min(x_ij, 1),  x_ij = a_i w_j,  a_i = fl32(w_i / S)
 //
 // (Sec. 3 gives the uncapped form w_i - w_i^2/S.)  Tiles: a workgroup owns
-// kEdRows rows (kEdRowsPerLane per lane, kEdLanes lanes) and one tile of
-// kEdCols columns; the column weights are wave-uniform, so they come through
+// kEdLanes R rows (R per lane, kEdLanes lanes) and one tile of C columns
+// (R, C: template parameters); the column weights are wave-uniform, so they come through
 // the scalar cache, sixteen at a time, and each pair costs three vector ops
 // (multiply, min, add).  Every row keeps four float32 accumulators over the
 // tile; tile partials are summed per row in float64 by a second kernel, which
@@ -23,10 +23,14 @@
 
 namespace cl {
 
+// Tile shape: kEdLanes threads per workgroup, R rows per thread, C columns
+// per tile.  R and C are schedule knobs (tile shapes of the instantiations
+// below; the default 2 x 1024); they change the float32 summation order of
+// the partials only within a tile of C columns.
 constexpr int kEdLanes = 256;
-constexpr int kEdRowsPerLane = 2;
-constexpr int kEdRows = kEdLanes * kEdRowsPerLane;
-constexpr int kEdCols = 1024;
+constexpr int kEdRowsDefault = 2;
+constexpr int kEdColsDefault = 1024;
+constexpr int kEdColsMin = 512;   // the workspace holds the partials of the smallest tile width
 constexpr int kEdUnroll = 16;
 
 __global__ void __launch_bounds__(256) k_rowscale(const float* __restrict__ w, uint64_t n, double S,
@@ -58,14 +62,15 @@ __global__ void __launch_bounds__(256) k_threshold(const float* __restrict__ a, 
 }
 
 // forward tile: part[tile * n + i] = sum_{j in tile} min(a_i w_j, 1) (float32).
-// Row i = blockIdx.x * kEdRows + r * kEdLanes + lane; column j of the tile
+// Row i = blockIdx.x * kEdLanes R + r * kEdLanes + lane; column j of the tile
 // goes to accumulator j mod 4 of every row.
+template <int R, int C>
 __global__ void __launch_bounds__(kEdLanes) k_expdeg_tile(const float* __restrict__ w, const float* __restrict__ a,
                                                           uint64_t n, float* __restrict__ part) {
-  constexpr int R = kEdRowsPerLane;
-  const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * kEdRows + threadIdx.x;
-  const uint64_t j0 = static_cast<uint64_t>(blockIdx.y) * kEdCols;
-  const uint64_t jn = (n - j0 < static_cast<uint64_t>(kEdCols)) ? (n - j0) : kEdCols;
+  static_assert(C % kEdUnroll == 0, "whole unrolled steps per tile");
+  const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * (kEdLanes * R) + threadIdx.x;
+  const uint64_t j0 = static_cast<uint64_t>(blockIdx.y) * C;
+  const uint64_t jn = (n - j0 < static_cast<uint64_t>(C)) ? (n - j0) : C;
   float ai[R], s[R][4];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -84,7 +89,7 @@ __global__ void __launch_bounds__(kEdLanes) k_expdeg_tile(const float* __restric
 #pragma unroll
       for (int r = 0; r < R; ++r) s[r][q & 3] += fminf(ai[r] * wv[q], 1.0f);
   }
-  // ragged tail of the last tile (kEdUnroll divides kEdCols)
+  // ragged tail of the last tile (kEdUnroll divides C)
 #pragma unroll
   for (int q = 0; q < kEdUnroll; ++q)
     if (jj + q < jn)
@@ -138,11 +143,9 @@ __device__ inline float mask_of(float wj, float t, const MaskRow& m) {
 // The mask (0.0 or 1.0) is applied with a fused multiply-add: w * 1 and g * 0
 // are exact, so each step rounds as the plain masked sum does (for finite g).
 // Column j goes to accumulator j mod 2 of every row.
-template <bool kFma>
+template <bool kFma, int R>
 __device__ inline void bwd_columns(const float* __restrict__ wc, const float* __restrict__ gc, uint64_t jn,
-                                   const float (&ti)[kEdRowsPerLane], const MaskRow (&mr)[kEdRowsPerLane],
-                                   float (&A)[kEdRowsPerLane][2], float (&B)[kEdRowsPerLane][2]) {
-  constexpr int R = kEdRowsPerLane;
+                                   const float (&ti)[R], const MaskRow (&mr)[R], float (&A)[R][2], float (&B)[R][2]) {
   uint64_t jj = 0;
   for (; jj + kEdUnroll <= jn; jj += kEdUnroll) {
     float wv[kEdUnroll], gv[kEdUnroll];
@@ -171,13 +174,14 @@ __device__ inline void bwd_columns(const float* __restrict__ wc, const float* __
       }
 }
 
+template <int R, int C>
 __global__ void __launch_bounds__(kEdLanes) k_expdeg_bwd_tile(const float* __restrict__ w, const float* __restrict__ thr,
                                                               const float* __restrict__ gw, uint64_t n,
                                                               float* __restrict__ partA, float* __restrict__ partB) {
-  constexpr int R = kEdRowsPerLane;
-  const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * kEdRows + threadIdx.x;
-  const uint64_t j0 = static_cast<uint64_t>(blockIdx.y) * kEdCols;
-  const uint64_t jn = (n - j0 < static_cast<uint64_t>(kEdCols)) ? (n - j0) : kEdCols;
+  static_assert(C % kEdUnroll == 0, "whole unrolled steps per tile");
+  const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * (kEdLanes * R) + threadIdx.x;
+  const uint64_t j0 = static_cast<uint64_t>(blockIdx.y) * C;
+  const uint64_t jn = (n - j0 < static_cast<uint64_t>(C)) ? (n - j0) : C;
   float ti[R], A[R][2], B[R][2];
   MaskRow mr[R];
   bool fast = true;
@@ -189,9 +193,9 @@ __global__ void __launch_bounds__(kEdLanes) k_expdeg_bwd_tile(const float* __res
     A[r][0] = A[r][1] = B[r][0] = B[r][1] = 0.0f;
   }
   if (__builtin_amdgcn_ballot_w64(!fast) == 0)
-    bwd_columns<true>(w + j0, gw + j0, jn, ti, mr, A, B);
+    bwd_columns<true, R>(w + j0, gw + j0, jn, ti, mr, A, B);
   else
-    bwd_columns<false>(w + j0, gw + j0, jn, ti, mr, A, B);
+    bwd_columns<false, R>(w + j0, gw + j0, jn, ti, mr, A, B);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint64_t i = i0 + static_cast<uint64_t>(r) * kEdLanes;

@@ -835,9 +835,30 @@ __device__ __forceinline__ double ln_one_minus_sel(double p, const Series& sr) {
 // (u, k)); a capped segment (p = 1) takes the next candidate without a skip.
 // Straight-line apart from the emission.  Kept edges go to emit(u, v); emit
 // returns false to end the unit.
+//
+// Capped runs: a lane at p = 1 lands on j itself, and while the pair (u, j)
+// is capped too (q = 1) the candidate is kept whatever the draw (r_acc < 1),
+// so such a step only consumes its draw index: no Philox block, logarithm or
+// division is needed.  Those lanes take the short branch and return; a
+// wavefront whose lanes are all inside capped runs skips the sampling
+// arithmetic altogether.  The draw index t still advances once per
+// candidate, so the first uncapped candidate after a run uses the same draw
+// as in the full step.
 template <class Emit>
 __device__ __forceinline__ void candidate_step(LaneRun& s, const LaneCtx& cx, const RoundKeys& rk,
                                                const Series& sr, Emit& emit, uint32_t& visits) {
+  if (s.p == 1.0 && cap1(s.a * cx.w[s.j]) == 1.0) {   // j < send while the segment is open
+    ++s.t;
+    if (!emit(s.u, s.j)) {
+      s.inseg = false;
+      s.sg = s.sg_end;
+      return;
+    }
+    ++visits;
+    s.j += 1;
+    s.inseg = (s.j < s.send);
+    return;
+  }
   const bool capped = (s.p == 1.0);
   const Block4 x = philox10(s.t, s.k, s.u, 0u, rk);
   ++s.t;
@@ -1101,9 +1122,15 @@ struct EmitOf<4> {
 // lane never waits for the slowest lane of a fixed group.  The lanes of a
 // wavefront work on one graph at a time (its parameters live in scalar
 // registers); a chunk of another graph is handed out once every lane is idle.
-template <int kMode>
+//
+// kStats (count pass only): each unit's record goes to stats[unit] (its lane,
+// the wave clock when it was taken and finished, its plan cost, candidates
+// and edges), for the comparison of unit policies; the header's candidate
+// total is left alone.
+template <int kMode, bool kStats = false>
 __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* out, uint64_t e_lo, uint64_t e_hi,
-                                                       uint32_t* deg, unsigned long long* rows) {
+                                                       uint32_t* deg, unsigned long long* rows, UnitStat* stats) {
+  static_assert(!kStats || kMode == 0, "statistics are recorded by the count pass");
   using Emit = typename EmitOf<kMode>::type;
   constexpr bool kWrite = (kMode == 1 || kMode == 2 || kMode == 4);
   constexpr bool kReplay = (kMode == 1 || kMode == 4);
@@ -1140,6 +1167,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
   unsigned long long* rowp = nullptr;   // CSR mode: the graph's row counts
   uint32_t cnext = 0, cend = 0, cgraph = kNone;
   bool queue_done = false;
+  gptr<uint64_t> costp{}, segp{};   // statistics: the graph's cost and segment prefixes
 
   // per lane
   uint32_t unit = kNone;
@@ -1151,6 +1179,9 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
   s.sg_end = 0;
   s.inseg = false;
   Emit em{};
+  uint64_t st_t0 = 0;        // statistics of the lane's current unit
+  uint32_t st_v0 = 0;
+  double st_cost = 0.0;
 
   while (true) {
     // (1) a lane that has finished its unit closes it
@@ -1158,6 +1189,12 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
     if (idle && unit != kNone) {
       if constexpr (kMode == 0) {
         lane_cnt[unit] = em.c;
+        if constexpr (kStats) {
+          const uint32_t wave = blockIdx.x * (kLaneThreads / 64) + threadIdx.x / 64;
+          stats[unit] = UnitStat{st_t0, __builtin_amdgcn_s_memrealtime(),
+                                 static_cast<uint32_t>(st_cost + 0.5), visits - st_v0, em.c,
+                                 wave * 64u + static_cast<uint32_t>(lane)};
+        }
       } else if constexpr (kMode == 2) {
         em.finish();
         lane_cnt[unit] = em.c;
@@ -1204,6 +1241,10 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
           nseg = uni32(static_cast<uint32_t>(d.SB1 - d.SB0));
           if constexpr (kMode == 3) degp = uniptr_mut(deg) + uni64(d.q_off);
           if constexpr (kMode == 4) rowp = uniptr_mut(rows) + uni64(d.q_off);
+          if constexpr (kStats) {
+            costp = to_global(uniptr(hdr->C) + uni64(d.r_off));
+            segp = to_global(uniptr(hdr->SB) + uni64(d.r_off));
+          }
         }
         // rank of this lane among the idle lanes
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(idle_mask >> 32),
@@ -1218,6 +1259,11 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
             s.sg = s.sg_end = 0;
           }
           s.inseg = false;
+          if constexpr (kStats) {
+            st_t0 = __builtin_amdgcn_s_memrealtime();
+            st_v0 = visits;
+            st_cost = 0.0;
+          }
           if constexpr (kMode == 0) {
             em = Emit{0u};
           } else if constexpr (kMode == 2) {
@@ -1245,12 +1291,18 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
       }
     }
     // (3) open the next segment of the unit
-    if (!s.inseg && s.more()) open_segment(s, cx);
+    if (!s.inseg && s.more()) {
+      open_segment(s, cx);
+      if constexpr (kStats) {   // the segment's share c_u / K_u of its source's plan cost
+        const uint32_t r = s.u - cx.u_begin;
+        st_cost += static_cast<double>(costp[r + 1] - costp[r]) / static_cast<double>(segp[r + 1] - segp[r]);
+      }
+    }
     if (!__any(s.inseg || s.more() || unit != kNone) && queue_done && cnext >= cend) break;
     // (4) one candidate step
     if (s.inseg) candidate_step(s, cx, rk, sr, em, visits);
   }
-  if (kMode == 0 || kMode == 2) {
+  if ((kMode == 0 && !kStats) || kMode == 2) {
     // candidates visited by the wavefront (statistics of the cost model)
     uint64_t visited = visits;
     for (int dd = 32; dd >= 1; dd >>= 1) visited += shfl_idx64(visited, lane ^ dd);

@@ -69,6 +69,16 @@ struct HSeg {
   uint32_t u, k, j, send;
 };
 
+// One work unit's record in the statistics pass (cl_unit_stats).
+struct UnitStat {
+  uint64_t t0, t1;   // wave clock (s_memrealtime, 100 MHz) when the lane took the unit / finished it
+  uint32_t cost;     // plan cost of the unit's segments, in cost units (kCostUnit per expected candidate)
+  uint32_t visits;   // candidates the unit visited
+  uint32_t edges;    // edges it kept
+  uint32_t lane;     // the lane that ran it: wavefront index * 64 + lane in the wavefront
+};
+static_assert(sizeof(UnitStat) == 32, "UnitStat is four 64-bit words");
+
 // Pointers into the workspace; copied into the workspace header so that
 // later calls need only the workspace base.
 struct WsHeader {

@@ -1,5 +1,7 @@
 """GPU: degrees of generated graphs without storing edges (cl_degrees),
 against the degree counts of the oracle's edge lists, bit-exact."""
+import math
+
 import numpy as np
 import pytest
 
@@ -182,3 +184,35 @@ def test_whole_graph_edges_part_by_part(cg, nparts):
     assert np.array_equal(np.concatenate([x for _, x in got]), want)
     res2 = parts.edges(_dev(w), S, 12, nparts)
     assert res2["digest"] == O.hash_edges(want)
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2])
+def test_unit_statistics_pass(cg, policy):
+    """cl_unit_stats over plans of all three unit policies (equal cost, equal
+    source counts, round robin): every unit has a record, the records add up
+    to the plan's candidates and edges (the oracle's) and to its total plan
+    cost, clocks are ordered; the plan's output is unchanged afterwards."""
+    w = W.config_plain(n=200_000)
+    S = O.exact_sum(w)
+    want, m, _, cand = O.generate(w, S, 21)
+    wd = _dev(w)
+    planner = cg.cl_plan if policy == 2 else cg.cl_sample
+    plan = planner([cg.Task(wd, S, 21)], tuning={"partition": policy})
+    st = cg.cl_unit_stats(plan)
+    info = cg.cl_plan_info(plan)
+    assert st["t0"].size == info["lanes"]
+    assert int(st["visits"].sum()) == cand
+    assert int(st["edges"].sum()) == m
+    assert bool((st["t1"] >= st["t0"]).all()) and bool((st["t0"] > 0).all())
+    # the segments' shares c_u / K_u add up to the lane plan's total cost,
+    # sum_u floor(16 e_u) + 16 K_u (rounded once per unit)
+    qs, Q = O.qscan(w)
+    Z = 0
+    for u in range(w.size):
+        e = O.ehat(w, S, u, Q=Q, qscale=qs)
+        K = O.segments(w, S, u, Q=Q, qscale=qs)[0] if e > O.E_SEG else 1
+        Z += math.floor(16.0 * e) + 16 * K
+    assert abs(int(st["cost"].sum()) - Z) <= st["cost"].size
+    if policy != 2:
+        got = cg.cl_generate(plan).cpu().numpy().view(np.uint32).reshape(-1, 2)[: plan.total]
+        assert np.array_equal(got, want)

@@ -170,3 +170,73 @@ def test_autotuner_keeps_output_and_picks_a_setting(cg, tmp_path, monkeypatch):
     assert res["best"]["lane_budget"] in (32, 192, 1024)
     assert len(res["table"]) == 6
     assert autotune.lookup(res["edges"]) == res["best"]
+
+
+def test_batch_autotuner_keeps_output_and_is_looked_up(cg, tmp_path, monkeypatch):
+    """tune_batch times replays of the captured batch for every setting
+    (raising if any changes the digest); its choice is what lookup returns
+    for batches of that size, and a batch captured with it is bit-exact with
+    the oracle."""
+    import torch
+    from paper_1406_1215_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tuned.json"))
+    rng = np.random.default_rng(12)
+    ws = [W.config_small(seed=int(rng.integers(1 << 30)), n=int(rng.integers(500, 30000))) for _ in range(6)]
+    tasks, wants = [], []
+    for i, w in enumerate(ws):
+        S = O.exact_sum(w)
+        wants.append(O.generate(w, S, 60 + i)[0])
+        tasks.append(cg.Task(_dev64(w), S, 60 + i))
+    res = autotune.tune_batch(tasks, budgets=(48, 192), blocks=(2, 4), reps=2)
+    assert len(res["table"]) == 4
+    m = sum(x.shape[0] for x in wants)
+    assert res["edges"] == m
+    assert autotune.lookup(m, kind="batch") == res["best"]
+    assert autotune.lookup(m) is None          # the plain tuner's entries are separate
+    plan = cg.cl_sample(tasks, tuning=res["best"])
+    s = torch.cuda.Stream()
+    bg = cg.cl_batch_capture(plan, s)
+    bg.launch(s)
+    s.synchronize()
+    got = bg.edges.cpu().numpy().view(np.uint32).reshape(-1, 2)[:m]
+    assert np.array_equal(got, np.concatenate(wants))
+    bg.close()
+
+
+SHAPES = [{"ed_rows": r, "ed_cols": c} for r in (1, 2, 4) for c in (512, 1024, 2048)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda t: f"R{t['ed_rows']}C{t['ed_cols']}")
+def test_every_tile_shape_matches_float64(cg, shape):
+    """Every tile shape the tuner may pick: forward and adjoint against the
+    float64 oracle at the same bars, on sizes with ragged row and column
+    tiles."""
+    for n in (2049, 5000):
+        w = _w32(n, 7 * n)
+        w64 = w.astype(np.float64)
+        S = float(np.sum(w64))
+        d = cg.cl_expected_degree(_dev32(w), S, tuning=shape).cpu().numpy()
+        ref = O.expdeg_brute(w64, S)
+        assert (np.abs(d - ref) / np.maximum(ref, 1e-300)).max() < 1e-5
+        g = np.random.default_rng(n).standard_normal(n)
+        got = cg.cl_expected_degree_backward(_dev32(w), S, _dev64(g), True, tuning=shape).cpu().numpy()
+        want = O.expdeg_grad_closed(w64, S, g, True)
+        assert np.linalg.norm(got.astype(np.float64) - want) / np.linalg.norm(want) < 1e-4
+
+
+def test_tile_shape_outside_the_instantiations_is_refused(cg):
+    w = _w32(100, 1)
+    for bad in ({"ed_rows": 3}, {"ed_cols": 256}, {"ed_cols": 4096}):
+        with pytest.raises(cg.ClError) as ei:
+            cg.cl_expected_degree(_dev32(w), float(w.sum()), tuning=bad)
+        assert ei.value.code == -1
+
+
+def test_expdeg_tuner_picks_a_shape_and_is_looked_up(cg, tmp_path, monkeypatch):
+    from paper_1406_1215_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tuned.json"))
+    w = _w32(20000, 5)
+    res = autotune.tune_expdeg(_dev32(w), float(w.astype(np.float64).sum()), reps=1)
+    assert len(res["table"]) == len(SHAPES)
+    assert res["best"] in SHAPES
+    assert autotune.lookup(20000.0 ** 2, kind="expdeg") == res["best"]

@@ -461,3 +461,44 @@ def test_csr_output(cg, planner, tuning):
 def torch_empty_i32(n):
     import torch
     return torch.empty(max(n, 1), dtype=torch.int32, device="cuda:0")
+
+
+def _capped_inputs():
+    rng = np.random.default_rng(77)
+    out = {}
+    # a capped clique at the head: 400 nodes with w^2 > S, then a power-law tail
+    head = np.full(400, 3000.0)
+    tail = np.minimum(np.sort(rng.pareto(1.5, 50000) + 1.0)[::-1] * 3.0, 2000.0)
+    out["clique head"] = np.concatenate([head, tail])
+    # the complete graph on 2048 nodes (w = n, every pair exactly capped), many segments per source
+    out["complete 2048"] = np.full(2048, 2048.0)
+    # the shape of the 1e9-node graph's head at a small size: mean 500, cap sqrt(500 n)
+    out["share shape"] = W.powerlaw_mean(200_000, 2.1, 500.0, np.random.default_rng(3))
+    # capped pairs that end inside segments: a slowly falling head
+    out["falling head"] = np.sort(rng.uniform(500.0, 4000.0, 3000))[::-1]
+    return out
+
+
+_CAPPED = {}
+
+
+def _capped_cases():
+    if not _CAPPED:
+        for name, w in _capped_inputs().items():
+            S = O.exact_sum(w)
+            want, m, _, cand = O.generate(w, S, 31)
+            _CAPPED[name] = (w, S, want, m, cand)
+    return _CAPPED
+
+
+@pytest.mark.parametrize("planner", PLANNERS)
+def test_capped_runs_bit_exact(planner, cg):
+    """Inputs dominated by capped pairs (p = 1), where runs of capped
+    candidates are taken without drawing random words: edge lists and the
+    visited-candidate count equal the oracle's."""
+    for name, (w, S, want, m, cand) in _capped_cases().items():
+        assert (w[0] / S) * w[min(10, w.size - 1)] >= 1.0, name     # the head is capped
+        got, plan = _gpu_edges(cg, w, S, 31, planner=planner)
+        assert plan.m == [m], name
+        assert np.array_equal(got, want), name
+        assert cg.cl_plan_info(plan)["candidates"] == cand, name
