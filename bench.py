@@ -12,30 +12,41 @@ second.  Printed as one JSON line, with:
 
 * roofline: the one-pass generation kernel (Alg. 1 per lane, edges staged
   into 64-byte chunks of per-lane slots), timed with HIP events on its stream.
-  Its bound is the memory system: every visited candidate reads one weight
-  w_v at an essentially random position (8 algorithmic bytes, one 128-byte
-  line from HBM or the Infinity Cache on an L2 miss) and every kept edge
-  writes a 4-byte slot word (v; a mark and u are added where the source
-  changes).  achieved = (8 B x candidates + 4 B x slot words) / launch time
-  against 8 TB/s; traffic = the kernel's measured HBM bytes (FETCH_SIZE +
-  WRITE_SIZE, scaled by a copy kernel of known size) from the committed
-  counter summary when it was taken on the current kernel source;
-  alu_view gives the same launch against the VALU peak;
+  Every visited candidate reads one weight w_v at an essentially random
+  position (8 algorithmic bytes, one 128-byte line from HBM or the Infinity
+  Cache on an L2 miss) and every kept edge writes a 4-byte slot word (v; a
+  mark and u are added where the source changes).  achieved = (8 B x
+  candidates + 4 B x slot words) / launch time against 8 TB/s; traffic = the
+  kernel's measured HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by a copy of
+  known size) from the committed counter summary when it was taken on the
+  current kernel source; ceilings = the same number of 8-byte gathers from
+  the same array alone (uniform positions, and positions drawn with the
+  candidates' density) and plain stores, measured in the same run
+  (libclceil.so), with the kernel's fraction of each;
+* alu_view: VALU wave-instructions of that kernel from the committed counter
+  summary against the issue capacity, and the counters' busy fraction;
 * hbm_write: bytes written per second by that kernel (slot words) and moved
   by the compaction (slot words read, 8-byte edges written), against 8 TB/s;
 * two_pass: the count-then-replay path (count pass, offsets, write pass);
-* expected_degree: the float32 tiled expected-degree kernel and its adjoint
-  on n = 1e5 (1e10 pairs), against the VALU lane-operation peak;
 * csr: the same plan written as compressed sparse rows (4-byte targets and
   row offsets) instead of (u, v) pairs;
-* calibration: 200 Adam steps on log w against n = 1e5 capped targets, then
-  generation from the calibrated weights;
 * partition_ablation: generation-kernel time with work units of equal
   expected cost (Eq. 5) vs units of equal source counts (Sec. 4's naive
-  consecutive partition), same number of units; and the degree kernel under
-  those two and round-robin units (Sec. 4's RRP);
-* batched: 256 uneven graphs in one captured HIP graph vs 256 plain calls;
-* cpu_baseline: the CPU oracle on a bounded sample of the same workload.
+  consecutive partition), same number of units; the degree kernel under
+  those two and round-robin units (Sec. 4's RRP); and per-unit statistics
+  of each (unit time against plan cost, wavefront balance);
+* expected_degree: the float32 tiled expected-degree kernel and its adjoint
+  on n = 1e5 (1e10 pairs), default and autotuned tile shape, against the
+  VALU lane-operation peak, with their errors against a float64 evaluation;
+* calibration: 200 Adam steps on log w against n = 1e5 capped targets, then
+  generation from the calibrated weights;
+* batched: 256 uneven graphs in one captured HIP graph (default and
+  autotuned schedule) vs 256 plain calls;
+* share: part 0 of 64 of the n = 1e9 graph (the paper's largest PL shape),
+  one pass and 4 output slabs through one buffer, digest checked against
+  the oracle's stored value;
+* cpu_baseline: the CPU oracle on bounded samples of the same workload, on
+  the process's CPU share and single-threaded, with the host's CPU model.
 """
 import argparse
 import hashlib
@@ -54,12 +65,16 @@ OPS_PER_CANDIDATE = 145          # operation count of one candidate step of the 
 # an FMA as two flops, i.e. 128 lanes per CU per clock x 256 CUs x 2.4 GHz.
 # Without packed fp32 math an FMA issues at half this rate.
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
+# wave64 VALU instructions per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 BYTES_PER_CANDIDATE = 8           # w_v gathered
 BYTES_PER_SLOT_WORD = 4           # slot words written: v per edge, (mark, u) per change of source
 BYTES_PER_EDGE = 8                # (u, v) uint32 pair of the edge list
 HBM_PEAK = 8.0e12                 # bytes/s
 METRIC = "edges/sec generated on 1 MI355X + % HBM write roofline; batched vs plain"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_generation_plain_1e7.json")
+SHARE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_generation_share_part0.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_generation_plain_1e7.json")
 KERNEL_SOURCES = ["cl_device.hpp", "cl_kernels.hpp", "cl_plan.hpp"]
 
 
@@ -96,6 +111,13 @@ def parse():
     ap.add_argument("--no-expdeg", action="store_true")
     ap.add_argument("--no-calib", action="store_true")
     ap.add_argument("--no-csr", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true")
+    ap.add_argument("--no-share", action="store_true")
+    ap.add_argument("--share-only", action="store_true",
+                    help="only the leg of part 0 of the n=1e9 graph (for profiling that launch)")
+    ap.add_argument("--no-tune", action="store_true", help="batched leg at the default schedule only")
+    ap.add_argument("--no-expdeg-ref", action="store_true",
+                    help="expected-degree leg without the float64 reference (for counter passes)")
     ap.add_argument("--full-graph-degrees", action="store_true",
                     help="instead of the step: the degree sequence of the whole n=1e9 graph (exponent 2.1, mean "
                          "degree 500), every edge generated and consumed on the fly, part by part")
@@ -135,6 +157,12 @@ def main():
     stream = torch.cuda.current_stream()
     if args.full_graph_degrees or args.full_graph_edges:
         print(json.dumps(bench_full_graph(args, cg, W, torch, np, dev)), flush=True)
+        return
+    if args.share_only:
+        out = bench_share(args, cg, W, torch, np, dev)
+        if args.copy_calibration:
+            out["copy_calibration_bytes"] = copy_calibration(torch, dev)
+        print(json.dumps(out), flush=True)
         return
 
     log("bench: generating the n=1e7 workload")
@@ -222,6 +250,8 @@ def main():
         "roofline": {
             "kernel": "one-pass generation (k_lanes<2>)",
             "bound": "hbm",
+            "limiter": "memory side: random 8-byte gathers of w_v, one 128-byte line per L2 miss, served mostly "
+                       "by the Infinity Cache; the rate of L2 line requests binds (see ceilings)",
             "achieved": achieved_bw / 1e9,
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
@@ -234,13 +264,7 @@ def main():
             "slot_words_per_launch": int(words),
             "launch_ms": t_gen * 1e3,
         },
-        "alu_view": {
-            "achieved": achieved_ops / 1e12,
-            "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "Top/s",
-            "frac": achieved_ops / PEAK_LANE_OPS,
-            "ops_per_candidate": OPS_PER_CANDIDATE,
-        },
+        "alu_view": alu_view(cand, t_gen),
         "hbm_write": {
             "generation_GBps": 4.0 * words / t_gen / 1e9,
             "generation_frac_of_8TBps": 4.0 * words / t_gen / HBM_PEAK,
@@ -250,16 +274,20 @@ def main():
             "whole_step_frac_of_8TBps": 8.0 * total_edges / elapsed / HBM_PEAK,
         },
     }
+    if not args.no_ceilings:
+        log("bench: memory ceilings")
+        result["roofline"]["ceilings"] = bench_ceilings(cg, torch, w, float(cg.cl_weight_sum(w)), cand, words, t_gen)
     if not args.no_two_pass:
         result["two_pass"] = bench_two_pass(args, cg, torch, w, seed, dev, stream)
     if not args.no_csr:
         result["csr"] = bench_csr(cg, torch, w, seed, plan, t_copy)
 
     if not args.no_ablation:
-        result["partition_ablation"] = bench_partition(cg, torch, w, seed)
+        result["partition_ablation"] = bench_partition(cg, torch, np, w, seed)
 
     if not args.no_expdeg:
-        result["expected_degree"] = bench_expdeg(cg, W, torch, dev)
+        result["expected_degree"] = bench_expdeg(cg, W, torch, dev, ref=not args.no_expdeg_ref,
+                                                 tune=not args.no_tune)
     if not args.no_calib:
         result["calibration"] = bench_calibration(cg, W, torch, dev)
 
@@ -267,25 +295,240 @@ def main():
         result["batched"] = bench_batched(args, cg, W, torch, np, dev)
 
     if args.copy_calibration:
-        # a plain device copy of 2 GiB whose source is not in any cache (a
-        # 2 GiB fill of another buffer runs in between): its FETCH_SIZE and
-        # WRITE_SIZE read 2 GiB each when the counters are exact
-        n8 = 1 << 28
-        x = torch.empty(n8, dtype=torch.float64, device=dev)
-        y = torch.empty_like(x)
-        z = torch.empty_like(x)
-        x.fill_(1.0)
-        z.fill_(2.0)
-        torch.cuda.synchronize()
-        y.copy_(x)
-        torch.cuda.synchronize()
-        result["copy_calibration_bytes"] = n8 * 8
-        del x, y, z
+        result["copy_calibration_bytes"] = copy_calibration(torch, dev)
+
+    if not args.no_share:
+        edges = None
+        plan = None
+        torch.cuda.empty_cache()
+        result["share"] = bench_share(args, cg, W, torch, np, dev)
 
     if not args.no_cpu:
         result["cpu_baseline"] = bench_cpu(w_np, seed)
 
     print(json.dumps(result), flush=True)
+
+
+def copy_calibration(torch, dev):
+    """A plain device copy of 2 GiB whose source is not in any cache (a
+    2 GiB fill of another buffer runs in between): its FETCH_SIZE and
+    WRITE_SIZE read 2 GiB each when the counters are exact, which scales the
+    counters of the other kernels of the same run."""
+    n8 = 1 << 28
+    x = torch.empty(n8, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    x.fill_(1.0)
+    z.fill_(2.0)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y, z
+    return n8 * 8
+
+
+def alu_view(cand, t_gen):
+    """The generation kernel against the vector ALU.  From the committed
+    rocprofv3 counter summary (taken on the current kernel source): VALU
+    wave-instructions per launch against the issue capacity of 256 CUs x 4
+    SIMDs, one wave64 instruction per 4 cycles each (16 lanes per SIMD: the
+    rate of float64 and of unpacked float32 operations) at 2.4 GHz, and the
+    counters' own busy fraction.  Without it, only the operation count of
+    one candidate step against the lane-operation peak."""
+    out = {"ops_per_candidate_estimate": OPS_PER_CANDIDATE,
+           "frac_estimate": cand * OPS_PER_CANDIDATE / t_gen / PEAK_LANE_OPS}
+    vc = valu_counters()
+    if vc:
+        insts = vc["valu_insts_per_launch"]
+        cap = VALU_ISSUE_PER_S
+        out.update({"source": os.path.relpath(VALU_FILE, ROOT),
+                    "valu_insts_per_launch": insts,
+                    "valu_insts_per_candidate": insts / max(cand, 1),
+                    "lane_ops_per_candidate": 64.0 * insts / max(cand, 1),
+                    "achieved": insts / t_gen / 1e9, "peak": cap / 1e9, "unit": "G wave-instructions/s",
+                    "frac": insts / t_gen / cap})
+        for k in ("valu_busy", "f64_share_of_valu"):
+            if k in vc:
+                out[k] = vc[k]
+    return out
+
+
+def candidate_density(torch, w, S):
+    """Expected candidate visits at each position v of a sorted weight
+    vector: sum over the sources u < v of min(w_u w_v / S, 1) (the visits of
+    kept edges; the rejected ones follow the same shape).  With w sorted,
+    the capped sources of v are a prefix u < J_v, J_v = #{u < v : w_u w_v >=
+    S}, so visits(v) = J_v + (w_v / S) (sum of w_u over J_v <= u < v)."""
+    n = w.numel()
+    P = torch.cumsum(w, 0)
+    Pex = P - w
+    thr = torch.where(w > 0, S / w, torch.full_like(w, float("inf")))
+    J = torch.searchsorted(-w, -thr, right=True)             # #{u : w_u >= S / w_v}
+    J = torch.minimum(J, torch.arange(n, device=w.device))
+    PJ = torch.where(J > 0, P[(J - 1).clamp(min=0)], torch.zeros_like(w))
+    return J.to(torch.float64) + (w / S) * (Pex - PJ)
+
+
+def draw_positions(torch, density, count, seed, chunk=1 << 25):
+    """count positions drawn independently with probability proportional to
+    density (inverse CDF), as int32."""
+    cdf = torch.cumsum(density, 0)
+    total = float(cdf[-1])
+    g = torch.Generator(device=density.device)
+    g.manual_seed(seed)
+    out = torch.empty(count, dtype=torch.int32, device=density.device)
+    for lo in range(0, count, chunk):
+        hi = min(count, lo + chunk)
+        r = torch.rand(hi - lo, dtype=torch.float64, device=density.device, generator=g) * total
+        out[lo:hi] = torch.searchsorted(cdf, r).clamp(max=density.numel() - 1).to(torch.int32)
+    return out
+
+
+def _time_ms(torch, fn, reps=3):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    best = float("inf")
+    for _ in range(reps):
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def bench_ceilings(cg, torch, w, S, cand, words, t_gen):
+    """Measured ceilings for the generation kernel (libclceil.so), on the same
+    device and weight array: `cand` 8-byte loads at uniform random positions,
+    the same number at positions drawn with the candidates' density
+    (candidate_density), and plain 16-byte stores; each the best over a few
+    grid sizes.  The kernel's fractions: ceiling time of its gathers (and of
+    its slot-word stores) over its own time."""
+    from paper_1406_1215_amd import ceilings as C
+    cus = int(cg.lib().cl_device_cus()) or 256
+    grids = [cus * k for k in (4, 8, 16)]
+    out = C.out_buffer(max(grids), w.device)
+    t_uni = min(_time_ms(torch, lambda b=b: C.gather_uniform(w, cand, 12345, b, out)) for b in grids)
+    idx = draw_positions(torch, candidate_density(torch, w, S), cand, 6789)
+    t_wgt = min(_time_ms(torch, lambda b=b: C.gather_list(w, idx, b, out)) for b in grids)
+    del idx
+    sbytes = 4 << 30
+    buf = torch.empty(sbytes, dtype=torch.uint8, device=w.device)
+    t_st = min(_time_ms(torch, lambda b=b: C.store(buf, b)) for b in grids)
+    del buf
+    store_bw = sbytes / (t_st * 1e-3)
+    t_words = BYTES_PER_SLOT_WORD * words / store_bw
+    return {
+        "loads": int(cand),
+        "gather_uniform_ms": t_uni,
+        "gather_uniform_loads_per_s": cand / (t_uni * 1e-3),
+        "gather_candidate_density_ms": t_wgt,
+        "gather_candidate_density_loads_per_s": cand / (t_wgt * 1e-3),
+        "store_GBps": store_bw / 1e9,
+        "store_frac_of_8TBps": store_bw / HBM_PEAK,
+        "kernel_frac_of_gather_uniform": t_uni * 1e-3 / t_gen,
+        "kernel_frac_of_gather_candidate_density": t_wgt * 1e-3 / t_gen,
+        "kernel_write_frac_of_store": t_words / t_gen,
+        "kernel_frac_of_memory_ceiling": (t_wgt * 1e-3 + t_words) / t_gen,
+    }
+
+
+def valu_counters():
+    """VALU counters of the generation kernel from the committed rocprofv3
+    summary, if it was taken on the current kernel source."""
+    try:
+        with open(VALU_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t
+
+
+def bench_share(args, cg, W, torch, np, dev):
+    """One GPU's share of the paper's largest PL shape: n = 1e9 weights
+    (exponent 2.1, mean degree 500, cap sqrt(500 n), weight seed 3), exact S,
+    the uniform consecutive partition into 64 parts (Eq. 5), part 0 (the
+    heavy head) generated with Philox seed 3 in one pass and written out in 4
+    slabs through one reused buffer.  Timed: plan + one pass + the 4 slab
+    expansions (the digest of each slab, standing in for the I/O the paper
+    leaves out, is outside the timed region).  The part's digest is compared
+    with the stored value of the oracle (tests/golden/share_part0.json)."""
+    log("bench: generating the n=1e9 weights")
+    w_np = W.config_share()
+    w = torch.from_numpy(w_np).to(dev)
+    del w_np
+    S = cg.cl_weight_sum(w)
+    P = 64
+    bounds, Z = cg.cl_partition(w, S, P)
+    u1 = bounds[1]
+    seed = 3
+    task = [cg.Task(w, S, seed, 0, u1)]
+    plan = cg.cl_sample(task)
+    m = plan.total
+    slab = (m + 3) // 4
+    buf = torch.empty((slab + 8, 2), dtype=torch.int32, device=dev)
+    acc = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def run(digest=False):
+        p = cg.cl_sample(task, ws=plan.ws)
+        for k in range(4):
+            b0 = k * slab
+            c = min(slab, m - b0)
+            cg.cl_generate(p, edges=buf, edge_begin=b0, cap=c)
+            if digest:
+                cg.cl_hash_edges(buf[:c], b0, acc)
+        return p
+
+    run()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p = run()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    info = cg.cl_plan_info(p)
+    lane_ms = info["lane_kernel_ms"]
+    acc.zero_()
+    run(digest=True)
+    digest = cg.hash_value(acc)
+    gold = None
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "share_part0.json")) as f:
+            gold = json.load(f)
+    except (OSError, ValueError):
+        pass
+    cand, words = info["candidates"], info["slot_words"]
+    alg = BYTES_PER_CANDIDATE * cand + BYTES_PER_SLOT_WORD * words
+    out = {
+        "workload": "n=1e9 power law, exponent 2.1, mean degree 500, cap sqrt(500 n), weight seed 3; part 0 of 64 "
+                    "(uniform consecutive partition, Eq. 5), Philox seed 3, 4 slabs through one buffer",
+        "sources": int(u1), "edges": int(m), "candidates": int(cand), "lanes": info["lanes"],
+        "seconds": el, "edges_per_s": m / el,
+        "lane_kernel_ms": lane_ms,
+        "roofline": {"kernel": "one-pass generation (k_lanes<2>)", "bound": "hbm",
+                     "achieved": alg / (lane_ms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": alg / (lane_ms * 1e-3) / HBM_PEAK, "algorithmic_bytes_per_launch": int(alg),
+                     "traffic": share_traffic()},
+        "digest": digest,
+        "digest_matches_oracle": (gold is not None and digest == gold["digest"] and m == gold["m"]),
+    }
+    del plan, p, buf, w
+    torch.cuda.empty_cache()
+    return out
+
+
+def share_traffic():
+    try:
+        with open(SHARE_TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def bench_full_graph(args, cg, W, torch, np, dev):
@@ -327,23 +570,56 @@ def bench_full_graph(args, cg, W, torch, np, dev):
     return out
 
 
-def bench_expdeg(cg, W, torch, dev, reps=5):
+def expdeg_reference(torch, w32, S, g, block=512):
+    """Float64 expected degrees and their gradient (S = sum of the weights,
+    so dS/dw_k = 1) by the definition, over all pairs in blocks of rows on
+    the GPU with plain torch float64 operations (no part of the kernels):
+    d_i = sum_{j != i} min(x_ij, 1), x_ij = w_i w_j / S, and
+    grad_k = (g_k A_k + B_k - T) / S with A_k = sum_{j != k, x_kj < 1} w_j,
+    B_k = sum_{j != k, x_kj < 1} g_j w_j, T = sum_i g_i sum_{j != i, x_ij < 1} x_ij."""
+    w = w32.double()
+    n = w.numel()
+    d = torch.empty(n, dtype=torch.float64, device=w.device)
+    A = torch.empty_like(d)
+    B = torch.empty_like(d)
+    U = torch.empty_like(d)
+    gw = g * w
+    for lo in range(0, n, block):
+        hi = min(n, lo + block)
+        X = w[lo:hi, None] * w[None, :] / S
+        r = torch.arange(hi - lo, device=w.device)
+        X[r, r + lo] = 0.0
+        d[lo:hi] = torch.clamp(X, max=1.0).sum(1)
+        M = (X < 1.0).double()
+        M[r, r + lo] = 0.0
+        A[lo:hi] = M @ w
+        B[lo:hi] = M @ gw
+        U[lo:hi] = (M * X).sum(1)
+    T = float(g @ U)
+    return d, (g * A + B - T) / S
+
+
+def bench_expdeg(cg, W, torch, dev, reps=5, ref=True, tune=True):
     """Expected degree d_i = sum_{j != i} min(w_i w_j / S, 1) and its adjoint
-    on n = 1e5 float32 weights (1e10 pairs each), timed with events; ALU
-    work 3 lane-operations per pair forward (multiply, min, add) and 3
-    backward (the clamped multiply-add that forms the mask, and one
-    multiply-add for each of the two sums; FMA-class, so at most half of
-    the lane-operation peak without packed math)."""
+    on n = 1e5 float32 weights (1e10 pairs each), timed with events, at the
+    default tile shape and at the autotuner's (tuned here once when its
+    cache has none); ALU work 3 lane-operations per pair forward (multiply,
+    min, add) and 3 backward (the clamped multiply-add that forms the mask,
+    and one multiply-add for each of the two sums; FMA-class, so at most half
+    of the lane-operation peak without packed math).  The errors of both
+    against the float64 definition (expdeg_reference): maximum relative
+    error of d, normwise relative error of the gradient."""
+    from paper_1406_1215_amd import autotune
     t = W.config_calib()
     w32 = torch.from_numpy(t.astype("float32")).to(dev)
     S = float(w32.double().sum().item())
     n = w32.numel()
-    g = torch.randn(n, dtype=torch.float64, device=dev)
+    g = torch.randn(n, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(17))
     ws = cg._ed_ws(n, dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     out = {"n": n, "pairs": n * n}
-    for name, fn, ops in (("forward", lambda: cg.cl_expected_degree(w32, S, ws=ws), 3),
-                          ("backward", lambda: cg.cl_expected_degree_backward(w32, S, g, True, ws=ws), 3)):
+
+    def timed(fn):
         fn()
         torch.cuda.synchronize()
         e0.record()
@@ -351,10 +627,31 @@ def bench_expdeg(cg, W, torch, dev, reps=5):
             fn()
         e1.record()
         e1.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        out[f"{name}_ms"] = ms
-        out[f"{name}_pairs_per_s"] = n * n / (ms * 1e-3)
-        out[f"{name}_alu_frac"] = n * n * ops / (ms * 1e-3) / PEAK_LANE_OPS
+        return e0.elapsed_time(e1) / reps
+
+    tuned = autotune.lookup(float(n) * n, kind="expdeg")
+    if tuned is None and tune:
+        log("bench: tuning the expected-degree tile shape")
+        tuned = autotune.tune_expdeg(w32, S, reps=2)["best"]
+    shapes = [("default", None)] + ([("tuned", tuned)] if tuned is not None else [])
+    for label, sh in shapes:
+        for name, fn, ops in (("forward", lambda: cg.cl_expected_degree(w32, S, ws=ws, tuning=sh), 3),
+                              ("backward", lambda: cg.cl_expected_degree_backward(w32, S, g, True, ws=ws,
+                                                                                  tuning=sh), 3)):
+            ms = timed(fn)
+            key = name if label == "default" else f"{name}_tuned"
+            out[f"{key}_ms"] = ms
+            out[f"{key}_pairs_per_s"] = n * n / (ms * 1e-3)
+            out[f"{key}_alu_frac"] = n * n * ops / (ms * 1e-3) / PEAK_LANE_OPS
+    out["tile_shape_tuned"] = tuned
+    if not ref:
+        return out
+    d = cg.cl_expected_degree(w32, S, ws=ws, tuning=tuned)
+    gr = cg.cl_expected_degree_backward(w32, S, g, True, ws=ws, tuning=tuned).double()
+    d_ref, gr_ref = expdeg_reference(torch, w32, S, g)
+    out["forward_max_rel_err_vs_f64"] = float((torch.abs(d - d_ref) / d_ref).max())
+    out["backward_normwise_rel_err_vs_f64"] = float(torch.linalg.norm(gr - gr_ref) / torch.linalg.norm(gr_ref))
+    out["backward_max_abs_err_over_max_abs"] = float(torch.abs(gr - gr_ref).max() / torch.abs(gr_ref).max())
     return out
 
 
@@ -401,12 +698,14 @@ def bench_calibration(cg, W, torch, dev, steps=200):
             "generation_edges": int(plan.total), "generation_ms": gen_s * 1e3}
 
 
-def bench_partition(cg, torch, w, seed):
+def bench_partition(cg, torch, np, w, seed):
     """Sec. 4's comparison on one GPU: work units of equal expected cost
     (Eq. 5 applied to lanes) vs units of equal numbers of sources, same unit
     count; generation-kernel time of each (same output).  Then the degree
     kernel under those two and round-robin units (RRP over segments), timed
-    with events around cl_degrees (which includes one small header read)."""
+    with events around cl_degrees (which includes one small header read),
+    and for each policy a statistics pass (unit_summary): unit time against
+    plan cost and the balance of the wavefronts."""
     S = cg.cl_weight_sum(w)
     out = {}
     for name, pol in (("equal_cost_ms", 0), ("equal_sources_ms", 1)):
@@ -441,7 +740,46 @@ def bench_partition(cg, torch, w, seed):
             ref = deg
         else:
             out["degrees_identical"] = out["degrees_identical"] and bool(torch.equal(deg, ref))
+        # per-unit times of a statistics pass (a count pass that records each
+        # unit's wave clock, plan cost and candidates)
+        out[f"units_{name}"] = unit_summary(cg.cl_unit_stats(plan), np)
         del plan
+    return out
+
+
+def unit_summary(st, np):
+    """Sec. 4's quantities from one statistics pass: unit run time against
+    plan cost and visited candidates (Pearson correlation, least-squares
+    time per cost unit), and the balance of the wavefronts: each one's span
+    from its first unit taken to its last unit finished, mean and maximum,
+    and the whole pass's span."""
+    t0 = st["t0"].astype(np.float64)
+    t1 = st["t1"].astype(np.float64)
+    cost = st["cost"].astype(np.float64)
+    vis = st["visits"].astype(np.float64)
+    work = cost > 0
+    tau = (t1 - t0) / 100.0            # microseconds (100 MHz clock)
+    out = {"units": int(work.sum())}
+    if work.sum() > 2:
+        c, v, t = cost[work], vis[work], tau[work]
+        out["corr_time_cost"] = float(np.corrcoef(t, c)[0, 1])
+        out["corr_time_candidates"] = float(np.corrcoef(t, v)[0, 1])
+        out["us_per_expected_candidate"] = float((t @ c) / (c @ c)) * 16.0
+        out["unit_us_mean"] = float(t.mean())
+        out["unit_us_max"] = float(t.max())
+        out["cost_max_over_mean"] = float(c.max() / c.mean())
+    wave = (st["lane"] // 64).astype(np.int64)
+    _, inv = np.unique(wave, return_inverse=True)
+    w0 = np.full(inv.max() + 1, np.inf)
+    w1 = np.zeros(inv.max() + 1)
+    np.minimum.at(w0, inv, t0)
+    np.maximum.at(w1, inv, t1)
+    span = (w1 - w0) / 100.0
+    out["waves"] = int(span.size)
+    out["wave_span_us_mean"] = float(span.mean())
+    out["wave_span_us_max"] = float(span.max())
+    out["wave_span_max_over_mean"] = float(span.max() / span.mean())
+    out["pass_span_us"] = float((t1.max() - t0.min()) / 100.0)
     return out
 
 
@@ -480,7 +818,10 @@ def bench_two_pass(args, cg, torch, w, seed, dev, stream):
 
 def bench_batched(args, cg, W, torch, np, dev):
     """256 uneven graphs: one captured HIP graph (whole path, no host sync)
-    vs 256 separate count + write calls, identical output checked by digest."""
+    vs 256 separate plain calls (cl_sample + cl_generate each), identical
+    output checked by digest.  The captured batch runs at the default
+    schedule and at the autotuner's choice (lane budget = chunk size of the
+    Eq. 5 split, persistent grid), both reported."""
     log("bench: generating the 256-graph batch")
     batch = W.config_batch()
     tasks = []
@@ -518,50 +859,107 @@ def bench_batched(args, cg, W, torch, np, dev):
     acc_plain.zero_()
     plain_pass(check=True)
 
-    plan = cg.cl_sample(tasks)
+    # the captured batch, at the default schedule and at the autotuned one
+    # (the tuner's cached choice for this output size, tuned here once when
+    # the cache has none)
+    from paper_1406_1215_amd import autotune
+    tuned = autotune.lookup(m_plain, kind="batch")
+    tune_s = 0.0
+    if tuned is None and not args.no_tune:
+        log("bench: tuning the batched launch")
+        t0 = time.perf_counter()
+        tuned = autotune.tune_batch(tasks)["best"]
+        tune_s = time.perf_counter() - t0
     s = torch.cuda.Stream()
-    bg = cg.cl_batch_capture(plan, s, cap=plan.total)
-    with torch.cuda.stream(s):
+    times = {}
+    same = True
+    edges = None
+    for name, tun in (("default", None), ("tuned", tuned)):
+        if name == "tuned" and tun is None:
+            continue
+        plan = cg.cl_sample(tasks, tuning=tun)
+        if edges is None:
+            edges = torch.empty((plan.total + 1024, 2), dtype=torch.int32, device=dev)
+        bg = cg.cl_batch_capture(plan, s, cap=plan.total, edges=edges)
         bg.launch(s)
-    s.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.batched_reps):
-        bg.launch(s)
-    s.synchronize()
-    t_batch = (time.perf_counter() - t0) / args.batched_reps
-    acc_b = torch.zeros(1, dtype=torch.int64, device=dev)
-    with torch.cuda.stream(s):
-        cg.cl_hash_edges(bg.edges[: plan.total], 0, acc_b, stream=s)
-    s.synchronize()
-    same = cg.hash_value(acc_b) == cg.hash_value(acc_plain) and plan.total == m_plain
-    bg.close()
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batched_reps):
+            bg.launch(s)
+        s.synchronize()
+        times[name] = (time.perf_counter() - t0) / args.batched_reps
+        acc_b = torch.zeros(1, dtype=torch.int64, device=dev)
+        with torch.cuda.stream(s):
+            cg.cl_hash_edges(edges[: plan.total], 0, acc_b, stream=s)
+        s.synchronize()
+        same = same and cg.hash_value(acc_b) == cg.hash_value(acc_plain) and plan.total == m_plain
+        bg.close()
+        del plan
+    t_batch = times.get("tuned", times["default"])
     return {
         "workload": "256 graphs, n log-uniform in [1e3,1e6], exponent U(2,3), mean degree U(4,64)",
-        "edges": int(plan.total),
+        "edges": int(m_plain),
         "plain_edges_per_s": m_plain / t_plain,
-        "batched_edges_per_s": plan.total / t_batch,
+        "batched_edges_per_s": m_plain / t_batch,
         "plain_ms": t_plain * 1e3,
         "batched_ms": t_batch * 1e3,
+        "batched_default_ms": times["default"] * 1e3,
+        "batched_tuned_ms": times["tuned"] * 1e3 if "tuned" in times else None,
+        "tuning": tuned,
+        "tuning_seconds": tune_s,
         "speedup": t_plain / t_batch,
         "identical_output": bool(same),
     }
 
 
+def cpu_info():
+    """Host CPU: logical CPUs the OS reports, the CPUs this process may run
+    on, and the model name."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "allowed_cpus": allowed, "model": model}
+
+
 def bench_cpu(w_np, seed):
-    """The oracle (as it stands) on the first half of the sources by cost
-    (uniform consecutive partition, P = 2, part 0): count + write passes."""
+    """The oracle (as it stands) on bounded samples of the same workload:
+    with the process's CPU share (at most 16 threads, the host share of one
+    GPU on this machine) the first half of the sources by cost (uniform
+    consecutive partition, P = 2, part 0), and single-threaded the first
+    sixteenth (P = 16, part 0); count + write passes, edges stored."""
     import oracle as O
+    info = cpu_info()
     S = O.exact_sum(w_np)
     bounds, _ = O.partition(w_np, S, 2)
     u1 = int(bounds[1])
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = max(1, min(16, info["allowed_cpus"]))
     log(f"bench: cpu oracle on sources [0, {u1}) with {threads} threads")
     t0 = time.perf_counter()
     _, m, _, _ = O.generate(w_np, S, seed, 0, u1, want_edges=True, nthreads=threads)
     dt = time.perf_counter() - t0
+    b16, _ = O.partition(w_np, S, 16)
+    v1 = int(b16[1])
+    log(f"bench: cpu oracle on sources [0, {v1}) with 1 thread")
+    t0 = time.perf_counter()
+    _, m1, _, _ = O.generate(w_np, S, seed, 0, v1, want_edges=True, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": m / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
             "sample": f"sources [0, {u1}) of the n=1e7 workload (first of 2 equal-cost partitions), "
-                      f"{m} edges, {dt:.1f} s"}
+                      f"{m} edges, {dt:.1f} s",
+            "host": info,
+            "single_thread": {"value": m1 / dt1, "unit": "edges/s", "cores": 1,
+                              "sample": f"sources [0, {v1}) (first of 16 equal-cost partitions), {m1} edges, "
+                                        f"{dt1:.1f} s"}}
 
 
 if __name__ == "__main__":

@@ -1,8 +1,9 @@
-"""Build libclgen.so (HIP, gfx950) in-tree.
+"""Build libclgen.so (HIP, gfx950) in-tree, and libclceil.so (the memory
+ceilings the benchmark measures beside the generation kernel).
 
-One translation unit (cl_api.hip includes the kernel headers).  Floating-point
-contraction is off so that every binary64 operation of the sampler is one
-IEEE-754 operation; packed fp32 instructions are disabled.
+One translation unit per library (cl_api.hip includes the kernel headers).
+Floating-point contraction is off so that every binary64 operation of the
+sampler is one IEEE-754 operation; packed fp32 instructions are disabled.
 """
 import os
 import subprocess
@@ -13,6 +14,8 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libclgen.so")
 SOURCES = ["cl_api.hip"]
+CEIL_LIB = os.path.join(PKG, "libclceil.so")
+CEIL_SOURCES = ["cl_ceilings.hip"]
 HEADERS = ["cl_device.hpp", "cl_plan.hpp", "cl_scan.hpp", "cl_kernels.hpp", "cl_stats.hpp", "cl_expdeg.hpp"]
 
 
@@ -23,20 +26,20 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def command(out: str):
+def command(out: str, sources=SOURCES):
     return [
         hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
         "-ffp-contract=off", "-fno-fast-math",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", os.path.join(ROOT, "include"), "-I", HERE,
-        *[os.path.join(HERE, s) for s in SOURCES],
+        *[os.path.join(HERE, s) for s in sources],
         "-o", out,
     ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
+def _build_one(lib: str, sources, verbose: bool) -> str:
+    tmp = lib + ".tmp"
+    cmd = command(tmp, sources)
     if verbose:
         print(" ".join(cmd))
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -46,8 +49,13 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed")
     if verbose and err.strip():
         sys.stderr.write(err + "\n")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    _build_one(CEIL_LIB, CEIL_SOURCES, verbose)
+    return _build_one(LIB, SOURCES, verbose)
 
 
 if __name__ == "__main__":
