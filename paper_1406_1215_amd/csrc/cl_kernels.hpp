@@ -835,30 +835,9 @@ __device__ __forceinline__ double ln_one_minus_sel(double p, const Series& sr) {
 // (u, k)); a capped segment (p = 1) takes the next candidate without a skip.
 // Straight-line apart from the emission.  Kept edges go to emit(u, v); emit
 // returns false to end the unit.
-//
-// Capped runs: a lane at p = 1 lands on j itself, and while the pair (u, j)
-// is capped too (q = 1) the candidate is kept whatever the draw (r_acc < 1),
-// so such a step only consumes its draw index: no Philox block, logarithm or
-// division is needed.  Those lanes take the short branch and return; a
-// wavefront whose lanes are all inside capped runs skips the sampling
-// arithmetic altogether.  The draw index t still advances once per
-// candidate, so the first uncapped candidate after a run uses the same draw
-// as in the full step.
 template <class Emit>
 __device__ __forceinline__ void candidate_step(LaneRun& s, const LaneCtx& cx, const RoundKeys& rk,
                                                const Series& sr, Emit& emit, uint32_t& visits) {
-  if (s.p == 1.0 && cap1(s.a * cx.w[s.j]) == 1.0) {   // j < send while the segment is open
-    ++s.t;
-    if (!emit(s.u, s.j)) {
-      s.inseg = false;
-      s.sg = s.sg_end;
-      return;
-    }
-    ++visits;
-    s.j += 1;
-    s.inseg = (s.j < s.send);
-    return;
-  }
   const bool capped = (s.p == 1.0);
   const Block4 x = philox10(s.t, s.k, s.u, 0u, rk);
   ++s.t;
