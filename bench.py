@@ -116,6 +116,9 @@ def parse():
     ap.add_argument("--share-only", action="store_true",
                     help="only the leg of part 0 of the n=1e9 graph (for profiling that launch)")
     ap.add_argument("--no-tune", action="store_true", help="batched leg at the default schedule only")
+    ap.add_argument("--inflight", type=int, default=1,
+                    help="also time the same steps with this many in flight (one host thread, stream, "
+                         "workspace and output buffer each)")
     ap.add_argument("--no-expdeg-ref", action="store_true",
                     help="expected-degree leg without the float64 reference (for counter passes)")
     ap.add_argument("--full-graph-degrees", action="store_true",
@@ -210,6 +213,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
+    inflight = None
+    if args.inflight > 1:
+        inflight = bench_inflight(args, cg, torch, w, seed, dev)
     # kernel times of the same step, outside the timed region (reading them
     # back costs a host round trip per step)
     copy_ms, lane_ms = [], []
@@ -274,6 +280,8 @@ def main():
             "whole_step_frac_of_8TBps": 8.0 * total_edges / elapsed / HBM_PEAK,
         },
     }
+    if inflight is not None:
+        result["inflight"] = inflight
     if not args.no_ceilings:
         log("bench: memory ceilings")
         result["roofline"]["ceilings"] = bench_ceilings(cg, torch, w, float(cg.cl_weight_sum(w)), cand, words, t_gen)
@@ -307,6 +315,54 @@ def main():
         result["cpu_baseline"] = bench_cpu(w_np, seed)
 
     print(json.dumps(result), flush=True)
+
+
+def bench_inflight(args, cg, torch, w, seed, dev):
+    """The same step (exact S, then plan + one pass + compaction in one
+    cl_sample_into call) with several steps in flight: one host thread per
+    pipeline, each with its own stream, workspaces and output buffer, the
+    steps dealt round robin; the library's host calls release the
+    interpreter while they wait, so the GPU runs one pipeline's plan and
+    compaction beside another's generation.  Whole-job edges per second."""
+    import threading
+    k = args.inflight
+    pipes = []
+    for _ in range(k):
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            S = cg.cl_weight_sum(w)
+            plan = cg.cl_sample([cg.Task(w, S, seed)])
+            edges = torch.empty((int(plan.total * 1.02) + 1024, 2), dtype=torch.int32, device=dev)
+            sws = torch.empty(cg.cl_weight_sum_workspace(w.numel()), dtype=torch.uint8, device=dev)
+        pipes.append({"stream": st, "plan": plan, "edges": edges, "sws": sws, "m": 0})
+
+    def run(p, nsteps):
+        with torch.cuda.stream(p["stream"]):
+            for _ in range(nsteps):
+                S = cg.cl_weight_sum(w, ws=p["sws"])
+                plan, fits = cg.cl_sample_into([cg.Task(w, S, seed)], p["edges"], ws=p["plan"].ws)
+                assert fits
+                p["plan"] = plan
+                p["m"] += plan.total
+
+    def round_(nsteps_total):
+        per = [nsteps_total // k + (1 if i < nsteps_total % k else 0) for i in range(k)]
+        th = [threading.Thread(target=run, args=(p, n)) for p, n in zip(pipes, per)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+
+    round_(max(args.warmup, k))
+    for p in pipes:
+        p["m"] = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    round_(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    m = sum(p["m"] for p in pipes)
+    return {"inflight": k, "steps": args.steps, "edges": m, "edges_per_s": m / el, "ms_per_step": el / args.steps * 1e3}
 
 
 def copy_calibration(torch, dev):
