@@ -46,7 +46,10 @@ second.  Printed as one JSON line, with:
   one pass and 4 output slabs through one buffer, digest checked against
   the oracle's stored value;
 * cpu_baseline: the CPU oracle on bounded samples of the same workload, on
-  the process's CPU share and single-threaded, with the host's CPU model.
+  the process's CPU share and single-threaded, with the host's CPU model;
+* inflight: the same steps with two in flight (two host threads, streams,
+  workspaces and output buffers), whole-job edges per second; `value` stays
+  the one-at-a-time figure.
 """
 import argparse
 import hashlib
@@ -116,9 +119,9 @@ def parse():
     ap.add_argument("--share-only", action="store_true",
                     help="only the leg of part 0 of the n=1e9 graph (for profiling that launch)")
     ap.add_argument("--no-tune", action="store_true", help="batched leg at the default schedule only")
-    ap.add_argument("--inflight", type=int, default=1,
+    ap.add_argument("--inflight", type=int, default=2,
                     help="also time the same steps with this many in flight (one host thread, stream, "
-                         "workspace and output buffer each)")
+                         "workspace and output buffer each); 1 = not at all")
     ap.add_argument("--no-expdeg-ref", action="store_true",
                     help="expected-degree leg without the float64 reference (for counter passes)")
     ap.add_argument("--full-graph-degrees", action="store_true",
