@@ -89,6 +89,13 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def expdeg_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1406_1215_amd", "csrc", "cl_expdeg.hpp"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def traffic_per_launch():
     """HBM bytes per launch of the write pass from the committed counter
     summary, if it was taken on the current kernel source."""
@@ -710,6 +717,16 @@ def bench_expdeg(cg, W, torch, dev, reps=5, ref=True, tune=True):
             out[f"{key}_pairs_per_s"] = n * n / (ms * 1e-3)
             out[f"{key}_alu_frac"] = n * n * ops / (ms * 1e-3) / PEAK_LANE_OPS
     out["tile_shape_tuned"] = tuned
+    # the tile kernels against the vector ALU from the committed counter
+    # summary (default tile shape, same kernel source): VALU wave-instructions
+    # per 64 pairs and rocprofv3's VALUBusy
+    vc = valu_counters()
+    if vc and vc.get("expdeg_hash") == expdeg_hash():
+        for name, key in (("forward", "expdeg_forward_tile"), ("backward", "expdeg_adjoint_tile")):
+            c = vc.get(key)
+            if c:
+                out[f"{name}_valu_insts_per_64_pairs"] = c["counters"]["SQ_INSTS_VALU"] / (n * n / 64.0)
+                out[f"{name}_valu_busy"] = c["valu_busy"]
     if not ref:
         return out
     d = cg.cl_expected_degree(w32, S, ws=ws, tuning=tuned)
