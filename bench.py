@@ -467,9 +467,10 @@ def bench_ceilings(cg, torch, w, S, cand, words, t_gen):
     """Measured ceilings for the generation kernel (libclceil.so), on the same
     device and weight array: `cand` 8-byte loads at uniform random positions,
     the same number at positions drawn with the candidates' density
-    (candidate_density) and the same positions on half the bytes per weight
-    (the footprint of a float32 copy), and plain 16-byte stores; each the
-    best over a few grid sizes.  The kernel's fractions: ceiling time of its gathers (and of
+    (candidate_density), the same positions on half the bytes per weight
+    (the footprint of a float32 copy) and the same positions visited band by
+    band (32 bands of v), and plain 16-byte stores; each the best over a few
+    grid sizes.  The kernel's fractions: ceiling time of its gathers (and of
     its slot-word stores) over its own time."""
     from paper_1406_1215_amd import ceilings as C
     cus = int(cg.lib().cl_device_cus()) or 256
@@ -481,6 +482,14 @@ def bench_ceilings(cg, torch, w, S, cand, words, t_gen):
     # the same positions on an array of half the bytes per weight (float32):
     # load 8 bytes at position idx // 2, so that every line holds the weights
     # of twice as many candidate positions
+    # the same positions visited band by band (32 bands of v, the order inside
+    # a band unchanged): the gathers of a traversal that keeps the whole chip
+    # in one band of w at a time
+    band = (idx.to(torch.int64) * 32) // w.numel()
+    banded = idx[torch.sort(band, stable=True).indices].contiguous()
+    del band
+    t_band = min(_time_ms(torch, lambda b=b: C.gather_list(w, banded, b, out)) for b in grids)
+    del banded
     idx.floor_divide_(2)
     t_half = min(_time_ms(torch, lambda b=b: C.gather_list(w, idx, b, out)) for b in grids)
     del idx
@@ -497,6 +506,7 @@ def bench_ceilings(cg, torch, w, S, cand, words, t_gen):
         "gather_candidate_density_ms": t_wgt,
         "gather_candidate_density_loads_per_s": cand / (t_wgt * 1e-3),
         "gather_candidate_density_half_footprint_ms": t_half,
+        "gather_candidate_density_32_bands_ms": t_band,
         "store_GBps": store_bw / 1e9,
         "store_frac_of_8TBps": store_bw / HBM_PEAK,
         "kernel_frac_of_gather_uniform": t_uni * 1e-3 / t_gen,
