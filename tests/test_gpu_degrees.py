@@ -216,3 +216,24 @@ def test_unit_statistics_pass(cg, policy):
     if policy != 2:
         got = cg.cl_generate(plan).cpu().numpy().view(np.uint32).reshape(-1, 2)[: plan.total]
         assert np.array_equal(got, want)
+
+
+def test_unit_statistics_errors(cg):
+    """cl_unit_stats: too short a record buffer is refused with the unit count
+    reported and nothing written; a workspace without a plan is refused."""
+    import ctypes
+    import torch
+    w = W.config_small(n=3000)
+    S = O.exact_sum(w)
+    plan = cg.cl_sample([cg.Task(_dev(w), S, 2)])
+    L = cg.lib()
+    units = ctypes.c_uint64(0)
+    buf = torch.full((8,), -1, dtype=torch.int64, device="cuda:0")
+    code = L.cl_unit_stats(ctypes.c_void_p(plan.ws.data_ptr()), None, ctypes.c_void_p(buf.data_ptr()), 8,
+                           ctypes.byref(units), None)
+    assert code == -7 and units.value == cg.cl_plan_info(plan)["lanes"] and units.value * 4 > 8
+    torch.cuda.synchronize()
+    assert bool((buf == -1).all())
+    empty = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda:0")
+    assert L.cl_unit_stats(ctypes.c_void_p(empty.data_ptr()), None, ctypes.c_void_p(buf.data_ptr()), 8, None,
+                           None) == -9

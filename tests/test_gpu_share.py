@@ -8,7 +8,8 @@ and position-keyed digest over all slabs equal the oracle's (stored in
 ``tests/golden/share_part0.json`` by ``tests/golden/make_golden.py``, which
 calls only the oracle); per-source edge lists bit-exact on sampled sources;
 sortedness / u < v / range across all slabs; the count-then-replay path gives
-the same digest."""
+the same digest.  And the largest node count the uint32 ids allow,
+n = 2^32 - 1, on the last sources of a constant-weight graph."""
 import json
 import os
 
@@ -112,3 +113,43 @@ def test_share_of_the_billion_node_graph(cg):
         e = cg.cl_generate(plan2, edges=buf, edge_begin=b0, cap=c)[:c]
         cg.cl_hash_edges(e, b0, acc2)
     assert cg.hash_value(acc1) == cg.hash_value(acc2)
+
+
+def test_largest_node_count(cg):
+    """n = 2^32 - 1, the largest graph the uint32 node ids allow (the source
+    mark 0xFFFFFFFF of the slots is then one above the largest id, and the
+    quantised prefix Q_n = n 2^32 is within 2^32 of 2^64): constant weights
+    2^28 (p = 2^28 / (2^32 - 1), about 1/16, for every pair), exact S, and the
+    edges of the last 2000 sources, element by element against the oracle,
+    from both planners; n = 2^32 is refused."""
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    if free < 100 * (1 << 30):
+        pytest.skip("needs ~100 GiB of device memory")
+    n = (1 << 32) - 1
+    print("max n: filling 2^32 - 1 weights", flush=True)
+    w = np.full(n, 2.0 ** 28)
+    S = O.exact_sum(w)
+    assert S == float(n) * 2.0 ** 28
+    wd = torch.from_numpy(w).to("cuda:0")
+    assert cg.cl_weight_sum(wd) == S
+    u0 = n - 2000
+    print("max n: oracle", flush=True)
+    want, m, _, cand = O.generate(w, S, 17, u0, n)
+    assert want[:, 1].max() == n - 1 and want[:, 0].min() >= u0
+    for planner in ("cl_sample", "cl_count"):
+        print(f"max n: {planner}", flush=True)
+        plan = getattr(cg, planner)([cg.Task(wd, S, 17, u0, n)])
+        assert plan.m == [m]
+        got = cg.cl_generate(plan).cpu().numpy().view(np.uint32).reshape(-1, 2)[:m]
+        assert np.array_equal(got, want), planner
+        assert cg.cl_plan_info(plan)["candidates"] == cand
+        del plan
+    del wd
+    torch.cuda.empty_cache()
+    # one more node is refused on the host, before any device work
+    import ctypes
+    g = (cg.cl_graph * 1)(cg.cl_graph(1, 1 << 32, 1.0, 1, 0, 0))
+    mm = (ctypes.c_uint64 * 1)()
+    req = ctypes.c_uint64(0)
+    assert cg.lib().cl_count(g, 1, None, None, 0, mm, ctypes.byref(req), None) == -5
