@@ -66,8 +66,10 @@ typedef struct cl_graph {
   uint64_t u_end;
 } cl_graph;
 
-/* Schedule knobs.  They change the launch schedule only, never an output bit.
- * Zero fields take the defaults. */
+/* Schedule knobs.  They change the launch schedule only, never an output bit
+ * of the generator (the expected-degree tile shape changes only the float32
+ * summation order of cl_expected_degree[_backward]).  Zero fields take the
+ * defaults. */
 typedef struct cl_tuning {
   uint32_t lane_budget;    /* expected candidates per lane (Eq. 5 chunk size), default 192 */
   uint32_t blocks_per_cu;  /* persistent grid = compute units x this (256-thread blocks), default 3 */
