@@ -209,9 +209,14 @@ def test_exact_sum_is_correctly_rounded():
 
 
 def test_mix64_known_values():
-    # splitmix64 (Steele, Lea, Flood, OOPSLA 2014): state 0 -> first output of the
-    # generator seeded with 0 is mix(0 + golden) = 0xE220A8397B1DCDAF
-    assert O.mix64(0) == 0xE220A8397B1DCDAF
+    # splitmix64 (Steele, Lea, Flood, OOPSLA 2014): the generator seeded with 0
+    # outputs mix(k * golden) for k = 1, 2, ...; its published first outputs
+    # are e220a8397b1dcdaf, 6e789e6aa1b965f4, 06c45d188009454f, f88bb8a8724c81ec
+    # (O.mix64(x) adds the golden increment to x itself)
+    golden = 0x9E3779B97F4A7C15
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    for k, v in enumerate(want):
+        assert O.mix64((k * golden) % (1 << 64)) == v
 
 
 def test_exact_sum_c_matches_fsum_and_fractions():
