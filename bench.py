@@ -7,8 +7,11 @@ inputs resident in HBM: exact sum S, plan (validation, quantised prefix,
 segments, lane plan), one pass of every lane into its slot (counting and
 writing), offsets, compaction of the slots into the contiguous edge list
 (after the first step, which allocates the output, plan + one pass +
-compaction are one call, cl_sample_into).  `value` is edges generated per
-second.  Printed as one JSON line, with:
+compaction are one call, cl_sample_into).  The schedule (lane budget, the
+Eq. 5 chunk size, and the persistent grid) is the autotuner's choice for
+this output size, tuned at the start when its cache has none
+(config.tuning).  `value` is edges generated per second.  Printed as one
+JSON line, with:
 
 * roofline: the one-pass generation kernel (Alg. 1 per lane, edges staged
   into 64-byte chunks of per-lane slots), timed with HIP events on its stream.
@@ -183,6 +186,21 @@ def main():
     w = torch.from_numpy(w_np).to(dev)
     seed = 2
 
+    # the schedule (lane budget = the Eq. 5 chunk size, persistent grid): the
+    # autotuner's cached choice for this output size, tuned here once (plan +
+    # one pass + expansion per setting, digest checked) when it has none
+    from paper_1406_1215_amd import autotune
+    S0 = cg.cl_weight_sum(w)
+    E0, _ = cg.cl_expected_edges(w, S0)
+    tuning = autotune.lookup(E0)
+    tune_s = 0.0
+    if tuning is None and not args.no_tune:
+        log("bench: tuning the plain step")
+        t0 = time.perf_counter()
+        tuning = autotune.tune([cg.Task(w, S0, seed)], planner="cl_sample", reps=4)["best"]
+        tune_s = time.perf_counter() - t0
+        torch.cuda.empty_cache()
+
     # one-pass path (the default): S, plan + one pass into slots, compaction
     edges = None
     plan = None
@@ -196,10 +214,10 @@ def main():
         nonlocal edges, plan
         S = cg.cl_weight_sum(w, ws=sum_ws)
         if fused and edges is not None:
-            plan, fits = cg.cl_sample_into([cg.Task(w, S, seed)], edges, ws=plan.ws)
+            plan, fits = cg.cl_sample_into([cg.Task(w, S, seed)], edges, ws=plan.ws, tuning=tuning)
             if fits:
                 return plan.total
-        plan = cg.cl_sample([cg.Task(w, S, seed)], ws=plan.ws if plan is not None else None)
+        plan = cg.cl_sample([cg.Task(w, S, seed)], ws=plan.ws if plan is not None else None, tuning=tuning)
         m = plan.total
         if args.verbose:
             log(f"bench: S = {S}, {m} edges")
@@ -225,7 +243,7 @@ def main():
     elapsed = t1 - t0
     inflight = None
     if args.inflight > 1:
-        inflight = bench_inflight(args, cg, torch, w, seed, dev)
+        inflight = bench_inflight(args, cg, torch, w, seed, dev, tuning)
     # kernel times of the same step, outside the timed region (reading them
     # back costs a host round trip per step)
     copy_ms, lane_ms = [], []
@@ -262,7 +280,8 @@ def main():
         "config": {"workload": f"plain CL, n={args.n:.0e}, power law exponent 2.1, w_min=10, capped at sqrt(S), "
                                f"Philox seed 2",
                    "n": int(w_np.size), "edges": int(m), "candidates": int(cand), "lanes": info["lanes"],
-                   "heavy_segments": info["heavy_segments"], "path": "one pass into slots + compaction"},
+                   "heavy_segments": info["heavy_segments"], "path": "one pass into slots + compaction",
+                   "tuning": tuning, "tuning_seconds": tune_s},
         "roofline": {
             "kernel": "one-pass generation (k_lanes<2>)",
             "bound": "hbm",
@@ -327,7 +346,7 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def bench_inflight(args, cg, torch, w, seed, dev):
+def bench_inflight(args, cg, torch, w, seed, dev, tuning=None):
     """The same step (exact S, then plan + one pass + compaction in one
     cl_sample_into call) with several steps in flight: one host thread per
     pipeline, each with its own stream, workspaces and output buffer, the
@@ -341,7 +360,7 @@ def bench_inflight(args, cg, torch, w, seed, dev):
         st = torch.cuda.Stream()
         with torch.cuda.stream(st):
             S = cg.cl_weight_sum(w)
-            plan = cg.cl_sample([cg.Task(w, S, seed)])
+            plan = cg.cl_sample([cg.Task(w, S, seed)], tuning=tuning)
             edges = torch.empty((int(plan.total * 1.02) + 1024, 2), dtype=torch.int32, device=dev)
             sws = torch.empty(cg.cl_weight_sum_workspace(w.numel()), dtype=torch.uint8, device=dev)
         pipes.append({"stream": st, "plan": plan, "edges": edges, "sws": sws, "m": 0})
@@ -350,7 +369,7 @@ def bench_inflight(args, cg, torch, w, seed, dev):
         with torch.cuda.stream(p["stream"]):
             for _ in range(nsteps):
                 S = cg.cl_weight_sum(w, ws=p["sws"])
-                plan, fits = cg.cl_sample_into([cg.Task(w, S, seed)], p["edges"], ws=p["plan"].ws)
+                plan, fits = cg.cl_sample_into([cg.Task(w, S, seed)], p["edges"], ws=p["plan"].ws, tuning=tuning)
                 assert fits
                 p["plan"] = plan
                 p["m"] += plan.total
