@@ -342,7 +342,7 @@ cl_status cl_batch_destroy(void* graph_exec);
 /* ---------------------------------------------------------------------------
  * Expected degrees under the capped model (Sec. 3, with j != i and the cap):
  *   d_i = sum_{j != i} min(w_i w_j / S, 1).
- * w: float32 (any order).  Pair terms in float32, accumulated in float32 over
+ * w: float32, non-negative (any order).  Pair terms in float32, accumulated in float32 over
  * tiles of columns; tile partials summed in float64.  d_out: float64.
  * ws: cl_expected_degree_workspace bytes.  Asynchronous.
  * ------------------------------------------------------------------------- */

@@ -5,8 +5,10 @@
 // (Sec. 3 gives the uncapped form w_i - w_i^2/S.)  Tiles: a workgroup owns
 // kEdLanes R rows (R per lane, kEdLanes lanes) and one tile of C columns
 // (R, C: template parameters); the column weights are wave-uniform, so they come through
-// the scalar cache, sixteen at a time, and each pair costs three vector ops
-// (multiply, min, add).  Every row keeps four float32 accumulators over the
+// the scalar cache, sixteen at a time, and each pair costs two vector ops:
+// the product with the clamp output modifier (min(x, 1) of a product that
+// is >= 0, as weights are non-negative: fmed3(x, 0, 1) folds into the
+// multiply) and the add.  Every row keeps four float32 accumulators over the
 // tile; tile partials are summed per row in float64 by a second kernel, which
 // also removes the j = i term.
 //
@@ -87,14 +89,14 @@ __global__ void __launch_bounds__(kEdLanes) k_expdeg_tile(const float* __restric
 #pragma unroll
     for (int q = 0; q < kEdUnroll; ++q)
 #pragma unroll
-      for (int r = 0; r < R; ++r) s[r][q & 3] += fminf(ai[r] * wv[q], 1.0f);
+      for (int r = 0; r < R; ++r) s[r][q & 3] += __builtin_amdgcn_fmed3f(ai[r] * wv[q], 0.0f, 1.0f);
   }
   // ragged tail of the last tile (kEdUnroll divides C)
 #pragma unroll
   for (int q = 0; q < kEdUnroll; ++q)
     if (jj + q < jn)
 #pragma unroll
-      for (int r = 0; r < R; ++r) s[r][q & 3] += fminf(ai[r] * wc[jj + q], 1.0f);
+      for (int r = 0; r < R; ++r) s[r][q & 3] += __builtin_amdgcn_fmed3f(ai[r] * wc[jj + q], 0.0f, 1.0f);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint64_t i = i0 + static_cast<uint64_t>(r) * kEdLanes;
@@ -110,7 +112,7 @@ __global__ void __launch_bounds__(256) k_expdeg_rows(const float* __restrict__ w
   if (i >= n) return;
   double s = 0.0;
   for (uint32_t t = 0; t < ntiles; ++t) s += static_cast<double>(part[static_cast<uint64_t>(t) * n + i]);
-  s -= static_cast<double>(fminf(a[i] * w[i], 1.0f));
+  s -= static_cast<double>(__builtin_amdgcn_fmed3f(a[i] * w[i], 0.0f, 1.0f));
   d[i] = s;
 }
 
