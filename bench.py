@@ -705,10 +705,11 @@ def bench_expdeg(cg, W, torch, dev, reps=5, ref=True, tune=True):
     """Expected degree d_i = sum_{j != i} min(w_i w_j / S, 1) and its adjoint
     on n = 1e5 float32 weights (1e10 pairs each), timed with events, at the
     default tile shape and at the autotuner's (tuned here once when its
-    cache has none); ALU work 3 lane-operations per pair forward (multiply,
-    min, add) and 3 backward (the clamped multiply-add that forms the mask,
-    and one multiply-add for each of the two sums; FMA-class, so at most half
-    of the lane-operation peak without packed math).  The errors of both
+    cache has none); ALU work 2 lane-operations per pair forward (the
+    multiply with the clamp modifier, the add) and 3 backward (the clamped
+    multiply-add that forms the mask, and one multiply-add for each of the
+    two sums; FMA-class, so at most half of the lane-operation peak without
+    packed math).  The errors of both
     against the float64 definition (expdeg_reference): maximum relative
     error of d, normwise relative error of the gradient."""
     from paper_1406_1215_amd import autotune
@@ -737,7 +738,7 @@ def bench_expdeg(cg, W, torch, dev, reps=5, ref=True, tune=True):
         tuned = autotune.tune_expdeg(w32, S, reps=2)["best"]
     shapes = [("default", None)] + ([("tuned", tuned)] if tuned is not None else [])
     for label, sh in shapes:
-        for name, fn, ops in (("forward", lambda: cg.cl_expected_degree(w32, S, ws=ws, tuning=sh), 3),
+        for name, fn, ops in (("forward", lambda: cg.cl_expected_degree(w32, S, ws=ws, tuning=sh), 2),
                               ("backward", lambda: cg.cl_expected_degree_backward(w32, S, g, True, ws=ws,
                                                                                   tuning=sh), 3)):
             ms = timed(fn)
