@@ -182,8 +182,10 @@ cl_status cl_sample_into(const cl_graph* g /* host, G entries */, uint32_t G, co
                          uint64_t* ws_required /* host, may be NULL */, void* stream);
 
 /* ---------------------------------------------------------------------------
- * For callers that cannot allocate device memory (code under HIP graph
- * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc; code that replays captured work can
+ * capture a counted plan with cl_batch_capture instead, since this call
+ * synchronises like cl_sample_into and so cannot itself be captured):
  * cl_sample_into with the workspace taken from a fixed array of
  * CL_NOALLOC_SCRATCH_BYTES in device memory that the library holds, one
  * copy per GPU, from the loading of the library until the process ends.
