@@ -11,6 +11,9 @@ HIP graph) against the oracle.
 * A batch whose last task is large enough for graded tail units (only the
   last task of a batch gets them): edge lists bit-exact with the oracle, with
   graded and with uniform units, plain and captured.
+* 200 seeded random small graphs of many kinds (ties, zero tails, capped
+  heads, constant weights, random source ranges) in one plan, plain and
+  captured, bit-exact with the oracle.
 """
 import json
 import os
@@ -153,3 +156,64 @@ def test_graded_tail_units_inside_a_batch(cg, planner):
         bg.close()
     # the last graph alone has >= 4096 uniform units, so grading applies to it
     assert lanes[1] >= 4096 and lanes[0] > lanes[1]
+
+
+def _random_graphs(seed, count):
+    """Seeded small weight vectors of many kinds: ties, zero tails, capped
+    heads, constant (ER), single nodes, heavy Pareto heads; each with a
+    random source range."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(1, 3000))
+        kind = int(rng.integers(0, 6))
+        if kind == 0:
+            w = np.sort(rng.pareto(float(rng.uniform(0.6, 2.5)), n) + 1.0)[::-1] * rng.uniform(0.1, 50.0)
+        elif kind == 1:
+            w = np.sort(rng.integers(0, 5, n).astype(np.float64))[::-1]
+        elif kind == 2:
+            w = np.full(n, float(rng.uniform(0.5, 40.0)))
+        elif kind == 3:
+            k = int(rng.integers(0, n + 1))
+            w = np.concatenate([np.sort(rng.uniform(1.0, 200.0, k))[::-1], np.zeros(n - k)])
+        elif kind == 4:
+            w = np.sort(rng.uniform(0.0, 1.0, n))[::-1] ** 3 * float(n)
+        else:
+            w = np.sort(rng.lognormal(2.0, 1.5, n))[::-1]
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        u0 = int(rng.integers(0, n + 1))
+        u1 = int(rng.integers(u0, n + 1))
+        if rng.random() < 0.5:
+            u0, u1 = 0, n
+        out.append((w, u0, u1, int(rng.integers(0, 1 << 62))))
+    return out
+
+
+@pytest.mark.parametrize("planner", ["cl_sample", "cl_count"])
+def test_many_random_small_graphs_in_one_batch(cg, planner):
+    """200 seeded random graphs of every kind in one plan, plain and replayed
+    from a captured graph: each graph's edge list equals the oracle's."""
+    import torch
+    cases = _random_graphs(123 if planner == "cl_sample" else 456, 200)
+    tasks, wants = [], []
+    for w, u0, u1, seed in cases:
+        S = O.exact_sum(w)
+        if S == 0.0:
+            S = 1.0
+        wants.append(O.generate(w, S, seed, u0, u1)[0])
+        tasks.append(cg.Task(_to_dev(w), S, seed, u0, u1))
+    plan = getattr(cg, planner)(tasks)
+    assert plan.m == [x.shape[0] for x in wants]
+    want = np.concatenate(wants)
+    go = torch.zeros(len(tasks) + 1, dtype=torch.int64, device="cuda:0")
+    got = _edges_np(cg.cl_generate(plan, graph_offsets=go))[: plan.total]
+    assert np.array_equal(got, want)
+    assert list(np.diff(go.cpu().numpy())) == plan.m
+    s = torch.cuda.Stream()
+    bg = cg.cl_batch_capture(plan, s)
+    bg.edges.fill_(-1)
+    torch.cuda.synchronize()
+    bg.launch(s)
+    s.synchronize()
+    assert np.array_equal(_edges_np(bg.edges)[: plan.total], want)
+    bg.close()
