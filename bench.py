@@ -81,7 +81,7 @@ METRIC = "edges/sec generated on 1 MI355X + % HBM write roofline; batched vs pla
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_generation_plain_1e7.json")
 SHARE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_generation_share_part0.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_generation_plain_1e7.json")
-KERNEL_SOURCES = ["cl_device.hpp", "cl_kernels.hpp", "cl_plan.hpp"]
+KERNEL_SOURCES = ["cl_device.hpp", "cl_kernels.hpp", "cl_plan.hpp", "cl_order.hpp"]
 
 
 def kernel_hash() -> str:
@@ -125,6 +125,8 @@ def parse():
     ap.add_argument("--no-calib", action="store_true")
     ap.add_argument("--no-csr", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
+    ap.add_argument("--no-order-ablation", action="store_true",
+                    help="skip the index-order runs of the generation kernel (profiles of the default order)")
     ap.add_argument("--no-share", action="store_true")
     ap.add_argument("--share-only", action="store_true",
                     help="only the leg of part 0 of the n=1e9 graph (for profiling that launch)")
@@ -311,6 +313,8 @@ def main():
     }
     if inflight is not None:
         result["inflight"] = inflight
+    if not args.no_order_ablation:
+        result["unit_order"] = bench_unit_order(cg, w, seed, tuning, t_gen)
     if not args.no_ceilings:
         log("bench: memory ceilings")
         result["roofline"]["ceilings"] = bench_ceilings(cg, torch, w, float(cg.cl_weight_sum(w)), cand, words, t_gen)
@@ -482,6 +486,27 @@ def _time_ms(torch, fn, reps=3):
     return best
 
 
+def lane_ms_of(cg, task, tuning, reps, ws=None):
+    """Lane-kernel times (HIP events, ms) of `reps` one-pass plans of one task."""
+    out = []
+    for _ in range(reps):
+        p = cg.cl_sample([task], tuning=tuning, ws=ws)
+        out.append(cg.cl_plan_info(p)["lane_kernel_ms"])
+        ws = p.ws
+    return out
+
+
+def bench_unit_order(cg, w, seed, tuning, t_gen):
+    """The generation kernel with its units taken in index order against the
+    default for one graph, by the position of their first candidate (the same
+    plan otherwise; the output is the same)."""
+    S = cg.cl_weight_sum(w)
+    idx = lane_ms_of(cg, cg.Task(w, S, seed), dict(tuning or {}, unit_order=1), 4)
+    pos_ms = t_gen * 1e3
+    return {"default": "by position (single graph)", "position_ms": pos_ms, "index_ms": sum(idx) / len(idx),
+            "index_over_position": sum(idx) / len(idx) / pos_ms}
+
+
 def bench_ceilings(cg, torch, w, S, cand, words, t_gen):
     """Measured ceilings for the generation kernel (libclceil.so), on the same
     device and weight array: `cand` 8-byte loads at uniform random positions,
@@ -593,6 +618,12 @@ def bench_share(args, cg, W, torch, np, dev):
     el = (time.perf_counter() - t0) / reps
     info = cg.cl_plan_info(p)
     lane_ms = info["lane_kernel_ms"]
+    order = None
+    if not args.no_order_ablation:
+        pos_ms = lane_ms_of(cg, task[0], None, 2, ws=plan.ws)
+        idx_ms = lane_ms_of(cg, task[0], {"unit_order": 1}, 2, ws=plan.ws)
+        order = {"default": "by position (single graph)", "position_ms": sum(pos_ms) / len(pos_ms),
+                 "index_ms": sum(idx_ms) / len(idx_ms), "index_over_position": sum(idx_ms) / sum(pos_ms)}
     acc.zero_()
     run(digest=True)
     digest = cg.hash_value(acc)
@@ -610,6 +641,7 @@ def bench_share(args, cg, W, torch, np, dev):
         "sources": int(u1), "edges": int(m), "candidates": int(cand), "lanes": info["lanes"],
         "seconds": el, "edges_per_s": m / el,
         "lane_kernel_ms": lane_ms,
+        "unit_order": order,
         "roofline": {"kernel": "one-pass generation (k_lanes<2>)", "bound": "hbm",
                      "achieved": alg / (lane_ms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": alg / (lane_ms * 1e-3) / HBM_PEAK, "algorithmic_bytes_per_launch": int(alg),

@@ -92,6 +92,14 @@ typedef struct cl_tuning {
   uint32_t ed_cols;        /* expected-degree tiles: columns per tile, 512, 1024 (default) or 2048;
                               other values of either: CL_ERR_INVALID_ARG.  The tile shape changes
                               only the float32 summation order inside a tile */
+  uint32_t unit_order;     /* order in which the lanes take the work units: 0 = default (2 for a
+                              single graph, 1 for a batch); 1 = index order; 2 = by the position of
+                              each unit's first candidate in the quantised prefix of w (512 bands of
+                              equal prefix mass; graded units in a second run after the others), so
+                              that the lanes in flight gather from a narrow stretch of w at a time and
+                              share its cache lines.  2 needs a single-graph plan (G > 1:
+                              CL_ERR_INVALID_ARG) and adds 4 bytes per unit and a count matrix to the
+                              workspace.  Other values: CL_ERR_INVALID_ARG */
 } cl_tuning;
 
 /* ---------------------------------------------------------------------------

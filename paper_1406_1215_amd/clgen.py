@@ -40,7 +40,7 @@ class cl_graph(ctypes.Structure):
 class cl_tuning(ctypes.Structure):
     _fields_ = [("lane_budget", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("slot_margin", ctypes.c_uint32), ("partition", ctypes.c_uint32), ("tail_units", ctypes.c_uint32),
-                ("ed_rows", ctypes.c_uint32), ("ed_cols", ctypes.c_uint32)]
+                ("ed_rows", ctypes.c_uint32), ("ed_cols", ctypes.c_uint32), ("unit_order", ctypes.c_uint32)]
 
 
 _lib = None
@@ -130,7 +130,7 @@ def _tuning(t: Optional[dict]):
     return ctypes.pointer(cl_tuning(int(t.get("lane_budget", 0)), int(t.get("blocks_per_cu", 0)),
                                     int(t.get("slot_margin", 0)), int(t.get("partition", 0)),
                                     int(t.get("tail_units", 0)), int(t.get("ed_rows", 0)),
-                                    int(t.get("ed_cols", 0))))
+                                    int(t.get("ed_cols", 0)), int(t.get("unit_order", 0))))
 
 
 def _f64(w: torch.Tensor) -> torch.Tensor:

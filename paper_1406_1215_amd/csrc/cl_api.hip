@@ -15,6 +15,7 @@
 #include "clgen.h"
 #include "cl_expdeg.hpp"
 #include "cl_kernels.hpp"
+#include "cl_order.hpp"
 #include "cl_plan.hpp"
 #include "cl_scan.hpp"
 #include "cl_stats.hpp"
@@ -115,10 +116,13 @@ FixedLayout fixed_layout(const cl_graph* g, uint32_t G) {
 struct VarLayout {
   uint64_t off_hseg, off_lstart, off_lcnt, off_lpos, off_lscan, off_groups, bytes;
   uint64_t off_lcum, off_soff, off_sscan, off_lwords, off_slots, slot_cap;
+  uint64_t off_perm, off_ohist, off_okeys, oblocks;
 };
 
-// nh heavy segments, nl lanes; with one_pass, slot_cap words of slots
-VarLayout var_layout(uint64_t base, uint64_t nh, uint64_t nl, bool one_pass, uint64_t slot_cap) {
+// nh heavy segments, nl lanes; with one_pass, slot_cap words of slots; with
+// ordered, the processing order of the units and its count matrix
+VarLayout var_layout(uint64_t base, uint64_t nh, uint64_t nl, bool one_pass, uint64_t slot_cap,
+                     bool ordered = false) {
   VarLayout V{};
   uint64_t off = align_up(base);
   V.off_hseg = off;
@@ -146,6 +150,15 @@ VarLayout var_layout(uint64_t base, uint64_t nh, uint64_t nl, bool one_pass, uin
     V.slot_cap = slot_cap;
     off = align_up(off + 4 * std::max<uint64_t>(slot_cap, 1));
   }
+  if (ordered) {
+    V.oblocks = order_blocks(nl);
+    V.off_perm = off;
+    off = align_up(off + 4 * std::max<uint64_t>(nl, 1));
+    V.off_ohist = off;
+    off = align_up(off + 4 * (2 * kOrderBins + 2));
+    V.off_okeys = off;
+    off = align_up(off + 2 * std::max<uint64_t>(nl, 1));
+  }
   V.bytes = off;
   return V;
 }
@@ -169,6 +182,16 @@ cl_status check_graphs(const cl_graph* g, uint32_t G) {
     if (g[i].u_begin > g[i].u_end || g[i].u_end > g[i].n) return CL_ERR_INVALID_ARG;
   }
   return CL_OK;
+}
+
+// processing order of a plan's units: 1 = index order, 2 = by position
+// (cl_tuning.unit_order; 0 takes 2 for a single graph, 1 for a batch)
+constexpr uint32_t kOrderRefused = 0xFFFFFFFFu;
+uint32_t ordered_units(const cl_tuning* t, uint32_t G) {
+  const uint32_t o = t ? t->unit_order : 0u;
+  if (o == 0) return (G == 1) ? 2u : 1u;
+  if (o > 2 || (o == 2 && G != 1)) return kOrderRefused;
+  return o;
 }
 
 uint64_t budget_units(const cl_tuning* t) {
@@ -205,6 +228,10 @@ hipError_t launch_plan_back(WsHeader* dhdr, const WsHeader& h, const cl_tuning* 
   hipLaunchKernelGGL(k_heavy_table, dim3(grid_for(h.cap_nh, 256, cap)), dim3(256), 0, s, dhdr);
   hipLaunchKernelGGL(k_lane_plan, dim3(grid_for(h.total_r, 256, cap)), dim3(256), 0, s, dhdr);
   hipLaunchKernelGGL(k_lane_groups, dim3(grid_for(h.cap_nl, 256, cap)), dim3(256), 0, s, dhdr);
+  {
+    hipError_t e = launch_order(dhdr, h, s);   // processing order of the units, if asked for
+    if (e != hipSuccess) return e;
+  }
   // (the unit queue and the overflow count were cleared with the status)
   if (h.mode == 2) {   // plan only (cl_plan): no lane kernel, no counts
     if (ev0) (void)hipEventRecord(ev0, s);
@@ -406,6 +433,7 @@ cl_status cl_workspace_size(const cl_graph* g, uint32_t G, const cl_tuning* t, u
                             uint64_t* fixed_bytes, uint64_t* estimate_bytes) {
   cl_status st = check_graphs(g, G);
   if (st != CL_OK) return st;
+  if (ordered_units(t, G) == kOrderRefused) return CL_ERR_INVALID_ARG;
   const FixedLayout F = fixed_layout(g, G);
   // estimate (when S = sum w): expected edges <= S/2, plan cost ~ 16 (S/2 + 2 range),
   // heavy segments ~ S/256
@@ -420,7 +448,8 @@ cl_status cl_workspace_size(const cl_graph* g, uint32_t G, const cl_tuning* t, u
   }
   const uint64_t nl64 = static_cast<uint64_t>(nl) / kLaneGroup * kLaneGroup + kLaneGroup * G;
   const VarLayout V = var_layout(F.bytes, static_cast<uint64_t>(nh), nl64, one_pass != 0,
-                                 one_pass ? slot_bound(static_cast<uint64_t>(cost), nl64, static_cast<uint64_t>(nseg)) : 0);
+                                 one_pass ? slot_bound(static_cast<uint64_t>(cost), nl64, static_cast<uint64_t>(nseg)) : 0,
+                                 ordered_units(t, G) == 2);
   if (fixed_bytes) *fixed_bytes = F.bytes;
   if (estimate_bytes) *estimate_bytes = V.bytes;
   return CL_OK;
@@ -476,6 +505,10 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
   const uint32_t policy = t ? t->partition : 0u;
   // round-robin units do not produce (u, v)-ordered runs: plan only
   if (policy > 2 || (policy == 2 && mode != 2)) return CL_ERR_INVALID_ARG;
+  // a processing order by position: single-graph plans (a chunk of units
+  // never spans two graphs); the default for them
+  const uint32_t order = ordered_units(t, G);
+  if (order == kOrderRefused) return CL_ERR_INVALID_ARG;
   const FixedLayout F = fixed_layout(g, G);
   if (ws_required) *ws_required = F.bytes;
   if (!ws || ws_bytes < F.bytes) return CL_ERR_WORKSPACE;
@@ -534,7 +567,8 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
 
   const bool one_pass = (mode == 1);
   const VarLayout V = var_layout(F.bytes, back.total_nh, back.total_nl, one_pass,
-                                 one_pass ? slot_bound(back.total_cost, back.total_nl, back.total_seg) : 0);
+                                 one_pass ? slot_bound(back.total_cost, back.total_nl, back.total_seg) : 0,
+                                 order == 2);
   if (ws_required) *ws_required = V.bytes;
   if (ws_bytes < V.bytes) return CL_ERR_WORKSPACE;
   h.cap_nh = back.total_nh;
@@ -565,6 +599,17 @@ static cl_status plan_common(const cl_graph* g, uint32_t G, const cl_tuning* t, 
     h.slot_scan_tmp = nullptr;
     h.slots = nullptr;
     h.slot_cap = 0;
+  }
+  if (order == 2) {
+    h.perm = reinterpret_cast<uint32_t*>(base + V.off_perm);
+    h.order_hist = reinterpret_cast<uint32_t*>(base + V.off_ohist);
+    h.order_keys = reinterpret_cast<uint16_t*>(base + V.off_okeys);
+    h.order_blocks = V.oblocks;
+  } else {
+    h.perm = nullptr;
+    h.order_hist = nullptr;
+    h.order_keys = nullptr;
+    h.order_blocks = 0;
   }
   h.status = 0;
   h.queue = 0;

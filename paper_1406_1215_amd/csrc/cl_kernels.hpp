@@ -1098,7 +1098,8 @@ struct EmitOf<4> {
 // handed out dynamically.  A wavefront takes chunks of 64 consecutive units
 // (all of one graph) from a global ticket counter, and each of its lanes takes
 // the next unit of the chunk as soon as it has finished its previous one, so a
-// lane never waits for the slowest lane of a fixed group.  The lanes of a
+// lane never waits for the slowest lane of a fixed group.  With a processing
+// order (perm, single-graph plans) the t-th unit handed out is perm[t].  The lanes of a
 // wavefront work on one graph at a time (its parameters live in scalar
 // registers); a chunk of another graph is handed out once every lane is idle.
 //
@@ -1133,6 +1134,8 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
   const gout<uint32_t> slots = to_global_mut(uniptr_mut(hdr->slots));
   const gout<uint32_t> lane_words = to_global_mut(uniptr_mut(hdr->lane_words));
   const gout<uint2> outw = to_global_mut(uniptr_mut(out));
+  const uint32_t* perm_p = uniptr(hdr->perm);   // processing order (null: index order)
+  const gptr<uint32_t> perm = to_global(perm_p);
   unsigned int* overflow = &hdr->overflow;
 
   // wave-uniform: the graph bound to the wavefront, its parameters, the chunk
@@ -1230,7 +1233,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_lanes(WsHeader* hdr, uint2* ou
                                                         __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(idle_mask), 0u));
         const uint32_t mine = cnext + rank;
         if (idle && mine < cend) {
-          unit = mine;
+          unit = perm_p ? perm[mine] : mine;
           s.sg = lane_seg[unit];
           s.sg_end = (rr || unit + 1 >= unit_end) ? nseg : lane_seg[unit + 1];
           if (s.sg > s.sg_end || s.sg_end > nseg) {   // never for a valid plan: flagged, nothing read

@@ -123,6 +123,13 @@ struct WsHeader {
   uint32_t planned;   // 1 after a successful count
   uint32_t pad2;
   double max_cost_check;
+  // processing order of the units by position (single-graph plans; cl_tuning
+  // unit_order 2, the default for one graph): perm[t] is the unit handed out
+  // t-th; null: index order
+  uint32_t* perm;          // [cap_nl]
+  uint32_t* order_hist;    // [2 kOrderBins] units per bin, then each bin's next free place
+  uint16_t* order_keys;    // [cap_nl] each unit's bin
+  uint64_t order_blocks;
 };
 
 }  // namespace cl

@@ -68,3 +68,24 @@ def test_host_side_argument_checks():
     bad = ctypes.pointer(clgen.cl_tuning(0, 0, 0, 3))
     assert L.cl_plan(g, 1, bad, None, 0, ctypes.byref(req), None) == -1
     assert L.cl_plan(g, 1, rr, None, 0, ctypes.byref(req), None) == -6   # accepted; workspace too small
+    # a processing order by position (the default for one graph): single-graph
+    # plans only; index order anywhere; unknown orders refused
+    by_pos = ctypes.pointer(clgen.cl_tuning(0, 0, 0, 0, 0, 0, 0, 2))
+    by_idx = ctypes.pointer(clgen.cl_tuning(0, 0, 0, 0, 0, 0, 0, 1))
+    assert L.cl_sample(g, 1, by_pos, None, 0, m, ctypes.byref(req), None) == -6   # accepted
+    g2 = (clgen.cl_graph * 2)(clgen.cl_graph(0, 0, 1.0, 1, 0, 0), clgen.cl_graph(0, 0, 1.0, 2, 0, 0))
+    m2 = (ctypes.c_uint64 * 2)()
+    assert L.cl_sample(g2, 2, by_pos, None, 0, m2, ctypes.byref(req), None) == -1
+    assert L.cl_count(g2, 2, by_pos, None, 0, m2, ctypes.byref(req), None) == -1
+    assert L.cl_sample(g2, 2, by_idx, None, 0, m2, ctypes.byref(req), None) == -6
+    assert L.cl_sample(g2, 2, None, None, 0, m2, ctypes.byref(req), None) == -6
+    odd = ctypes.pointer(clgen.cl_tuning(0, 0, 0, 0, 0, 0, 0, 3))
+    assert L.cl_sample(g, 1, odd, None, 0, m, ctypes.byref(req), None) == -1
+    assert L.cl_workspace_size(g, 1, odd, 1, ctypes.byref(fixed), ctypes.byref(est)) == -1
+    # the ordered plan's workspace estimate covers the order's arrays
+    est1 = ctypes.c_uint64(0)
+    assert L.cl_workspace_size(g, 1, by_pos, 1, ctypes.byref(fixed), ctypes.byref(est1)) == 0
+    assert L.cl_workspace_size(g, 1, None, 1, ctypes.byref(fixed), ctypes.byref(est)) == 0
+    assert est1.value == est.value
+    assert L.cl_workspace_size(g, 1, by_idx, 1, ctypes.byref(fixed), ctypes.byref(est)) == 0
+    assert est1.value > est.value

@@ -7,8 +7,9 @@ out in 4 slabs.  Checked: partition bounds bit-exact; the part's edge count
 and position-keyed digest over all slabs equal the oracle's (stored in
 ``tests/golden/share_part0.json`` by ``tests/golden/make_golden.py``, which
 calls only the oracle); per-source edge lists bit-exact on sampled sources;
-sortedness / u < v / range across all slabs; the count-then-replay path gives
-the same digest.  And the largest node count the uint32 ids allow,
+sortedness / u < v / range across all slabs; the count-then-replay path with
+the units in index order (the one-pass plan takes them by position) gives the
+same digest.  And the largest node count the uint32 ids allow,
 n = 2^32 - 1, on the last sources of a constant-weight graph."""
 import json
 import os
@@ -103,8 +104,9 @@ def test_share_of_the_billion_node_graph(cg):
     assert cg.hash_value(acc1) == gold["digest"]
     del plan
     torch.cuda.empty_cache()
-    # the count-then-replay path gives the same digest
-    plan2 = cg.cl_count([cg.Task(wd, S, seed, 0, u1)])
+    # the count-then-replay path, with the units taken in index order instead
+    # of by position, gives the same digest
+    plan2 = cg.cl_count([cg.Task(wd, S, seed, 0, u1)], tuning={"unit_order": 1})
     assert plan2.total == m
     acc2 = torch.zeros(1, dtype=torch.int64, device="cuda:0")
     for s in range(4):
