@@ -59,6 +59,9 @@ CASES = {
     "zero_tail": lambda: (np.concatenate([_pareto(2000, 9, 60.0), np.zeros(500)]), 0, None),
     "range": lambda: (_pareto(30000, 61, 40.0), 17, 9000),
     "single": lambda: (np.array([5.0]), 0, None),
+    "all_zero": lambda: (np.zeros(10), 0, None),
+    "empty_range": lambda: (_pareto(3000, 62, 40.0), 500, 500),
+    "last_sources": lambda: (_pareto(20000, 63, 40.0), 19990, 20000),
 }
 TUNINGS = [None, {"unit_order": 1}, {"unit_order": 2}, {"unit_order": 2, "lane_budget": 17},
            {"unit_order": 2, "tail_units": 1}]
@@ -69,7 +72,7 @@ TUNINGS = [None, {"unit_order": 1}, {"unit_order": 2}, {"unit_order": 2, "lane_b
 def test_orders_bit_exact(cg, planner, case):
     w, u0, u1 = CASES[case]()
     u1 = w.size if u1 is None else u1
-    S = O.exact_sum(w)
+    S = O.exact_sum(w) or 1.0
     want, m, _, cand = O.generate(w, S, 4, u0, u1)
     wd = _dev(w)
     for tun in TUNINGS:
