@@ -128,6 +128,8 @@ def parse():
     ap.add_argument("--no-order-ablation", action="store_true",
                     help="skip the index-order runs of the generation kernel (profiles of the default order)")
     ap.add_argument("--no-share", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 256-graph batch: the captured launch against 256 separate calls")
     ap.add_argument("--share-only", action="store_true",
                     help="only the leg of part 0 of the n=1e9 graph (for profiling that launch)")
     ap.add_argument("--no-tune", action="store_true", help="batched leg at the default schedule only")
@@ -175,6 +177,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.full_graph_degrees or args.full_graph_edges:
         print(json.dumps(bench_full_graph(args, cg, W, torch, np, dev)), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps(bench_batched(args, cg, W, torch, np, dev)), flush=True)
         return
     if args.share_only:
         out = bench_share(args, cg, W, torch, np, dev)
