@@ -66,6 +66,17 @@ __device__ __forceinline__ uint32_t find_graph(uint32_t G, uint64_t i, F off) {
   return lo;
 }
 
+// largest g in [lo, hi] with off(g) <= i (off(lo) <= i)
+template <class F>
+__device__ __forceinline__ uint32_t find_graph_in(uint32_t lo, uint32_t hi, uint64_t i, F off) {
+  uint32_t h = hi + 1;
+  while (h - lo > 1) {
+    const uint32_t mid = (lo + h) >> 1;
+    if (off(mid) <= i) lo = mid; else h = mid;
+  }
+  return lo;
+}
+
 // first v in [lo, hi] with Qrel(v) >= target; Qrel(hi) >= target is assumed
 __device__ __forceinline__ uint64_t q_lower_bound(const uint64_t* Q, uint64_t q_off, uint64_t Qbase,
                                                   uint64_t lo, uint64_t hi, uint64_t target) {
@@ -106,6 +117,7 @@ __device__ __forceinline__ void bin_flush(unsigned long long* lds, int b, uint64
 // are read once and its flags ORed once per thread; each thread handles
 // kValUnroll slots per step, their loads issued together.
 constexpr int kValUnroll = 4;
+constexpr uint64_t kValTile = 256 * kValUnroll;   // slots per tile (several graphs)
 
 struct ValView {
   const double* w;
@@ -130,25 +142,22 @@ __global__ void __launch_bounds__(256) k_validate(GraphDesc* desc, uint32_t G, u
   uint32_t flags0 = 0;     // single graph: its flags, ORed at the end
   int cur_b = -1;
   uint64_t acc_lo = 0, acc_hi = 0;
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i0 < total_slots;
-       i0 += kValUnroll * stride) {
+  // kValUnroll slots idx[r] of graphs dv[r] (idx >= total_slots: none), their
+  // loads issued together
+  auto step = [&](const uint64_t (&idx)[kValUnroll], const ValView (&dv)[kValUnroll]) {
     double x[kValUnroll], y[kValUnroll];
-    ValView dv[kValUnroll];
     bool live[kValUnroll];
 #pragma unroll
     for (int r = 0; r < kValUnroll; ++r) {
-      const uint64_t i = i0 + r * stride;
-      dv[r] = (G == 1) ? v0 : view(find_graph(G, i < total_slots ? i : 0, [&](uint32_t q) { return desc[q].q_off; }));
-      const uint64_t v = i - dv[r].q_off;
-      live[r] = (i < total_slots) && (v < dv[r].n);
+      const uint64_t v = idx[r] - dv[r].q_off;
+      live[r] = (idx[r] < total_slots) && (v < dv[r].n);
       x[r] = live[r] ? dv[r].w[v] : 0.0;
       y[r] = (live[r] && v + 1 < dv[r].n) ? dv[r].w[v + 1] : 0.0;
     }
 #pragma unroll
     for (int r = 0; r < kValUnroll; ++r) {
       if (!live[r]) continue;
-      const uint64_t v = i0 + r * stride - dv[r].q_off;
+      const uint64_t v = idx[r] - dv[r].q_off;
       const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(x[r]));
       const uint32_t ex = static_cast<uint32_t>((bits >> 52) & 0x7FF);
       uint32_t flag = 0;
@@ -179,6 +188,43 @@ __global__ void __launch_bounds__(256) k_validate(GraphDesc* desc, uint32_t G, u
         if (G == 1) flags0 |= flag;
         else atomicOr(&desc[dv[r].g].status, flag);
       }
+    }
+  };
+  uint64_t idx[kValUnroll];
+  ValView dv[kValUnroll];
+  if (G == 1) {
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i0 < total_slots;
+         i0 += kValUnroll * stride) {
+#pragma unroll
+      for (int r = 0; r < kValUnroll; ++r) {
+        idx[r] = i0 + r * stride;
+        dv[r] = v0;
+      }
+      step(idx, dv);
+    }
+  } else {
+    // several graphs: tiles of kValTile consecutive slots; a tile inside one
+    // graph reads that graph's fields once, by block-uniform loads, and a
+    // tile across graphs searches only the graphs it spans
+    auto qoff = [&](uint32_t q) { return desc[q].q_off; };
+    const uint64_t ntiles = (total_slots + kValTile - 1) / kValTile;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+      const uint64_t tb = tile * kValTile;
+      const uint64_t te = ((tb + kValTile < total_slots) ? tb + kValTile : total_slots) - 1;
+      const uint32_t g0 = uni32(find_graph(G, tb, qoff));
+      const uint32_t g1 = uni32(find_graph_in(g0, G - 1, te, qoff));
+#pragma unroll
+      for (int r = 0; r < kValUnroll; ++r) idx[r] = tb + static_cast<uint64_t>(r) * blockDim.x + threadIdx.x;
+      if (g0 == g1) {
+        const ValView vg = view(g0);
+#pragma unroll
+        for (int r = 0; r < kValUnroll; ++r) dv[r] = vg;
+      } else {
+#pragma unroll
+        for (int r = 0; r < kValUnroll; ++r) dv[r] = view(find_graph_in(g0, g1, idx[r] < te ? idx[r] : te, qoff));
+      }
+      step(idx, dv);
     }
   }
   if (flags0) atomicOr(&desc[0].status, flags0);
@@ -663,75 +709,121 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
 // Each thread takes kPlanUnroll sources per step, their loads (weight and
 // cost prefixes) issued together before any of them is used.  A single
 // graph has its own instance (kOne) with no per-source descriptor loads,
-// whose waits would also wait for the stores in flight.
+// whose waits would also wait for the stores in flight.  Several graphs are
+// walked in tiles of kPlanTile consecutive sources: a tile inside one graph
+// reads that graph's fields once, by block-uniform loads; a tile across
+// graphs searches only the graphs it spans.
 constexpr int kPlanUnroll = 4;
+constexpr uint64_t kPlanTile = 256 * kPlanUnroll;
+
+// the workspace arrays the lane plan reads and writes, read once per thread
+struct PlanArrays {
+  uint64_t total_r;
+  gptr<uint64_t> C, SB;
+  gout<double> A;
+  gout<uint32_t> lane_seg;
+  gout<uint64_t> lane_cum;
+};
+
+// one step over the sources idx[q] (idx >= total_r: none); ctx(q) gives
+// item q's graph fields
+template <class Ctx>
+__device__ __forceinline__ void plan_sources_step(const PlanArrays& pa, const uint64_t (&idx)[kPlanUnroll], Ctx ctx) {
+  const uint64_t total_r = pa.total_r;
+  const gptr<uint64_t> C = pa.C;
+  const gptr<uint64_t> SB = pa.SB;
+  const gout<double> A = pa.A;
+  const gout<uint32_t> lane_seg = pa.lane_seg;
+  const gout<uint64_t> lane_cum = pa.lane_cum;
+  bool live[kPlanUnroll];
+  double wu[kPlanUnroll];
+  uint64_t cl[kPlanUnroll], ch[kPlanUnroll];
+#pragma unroll
+  for (int q = 0; q < kPlanUnroll; ++q) {
+    const uint64_t i = idx[q];
+    const PlanCtx d = ctx(q);
+    const uint64_t r = i - d.r_off;
+    live[q] = (i < total_r) && (r < d.nr);   // r < nr: C[i + 1] is the graph's own
+    wu[q] = live[q] ? to_global(d.w)[d.u_begin + r] : 0.0;
+    cl[q] = live[q] ? C[i] : 0;
+    ch[q] = live[q] ? C[i + 1] : 0;
+  }
+  // the unit starts of the one-segment sources (graph-relative segment
+  // NH + r - H), computed before any store: a wait for a load also waits
+  // for the stores issued before it
+  double flo[kPlanUnroll], fhi[kPlanUnroll];
+  uint64_t seg[kPlanUnroll];
+#pragma unroll
+  for (int q = 0; q < kPlanUnroll; ++q) {
+    flo[q] = 0.0;
+    fhi[q] = 0.0;
+    seg[q] = 0;
+    if (!live[q]) continue;
+    const uint64_t i = idx[q];
+    const PlanCtx d = ctx(q);
+    const uint64_t r = i - d.r_off;
+    if (d.equal_cost_units()) {
+      if (r < d.H) continue;   // claimed segment by segment with the heavy table
+      flo[q] = (r == 0) ? -1.0 : d.unit_at(static_cast<double>(cl[q] - d.C0));
+      fhi[q] = d.unit_at(static_cast<double>(ch[q] - d.C0));
+      seg[q] = d.NH + (r - d.H);
+    } else if (d.L != 0 && d.policy == 1) {
+      // equal source counts: unit li starts at source floor(li nr / L), segment 0
+      // (L <= nr, so a source starts at most one unit); round-robin starts
+      // (policy 2) are set with the groups
+      const uint64_t L = d.L;
+      const uint64_t li = (r * L + d.nr - 1) / d.nr;          // ceil(r L / nr)
+      if (li < L && (li * d.nr) / L == r) {
+        flo[q] = static_cast<double>(li) - 1.0;
+        fhi[q] = static_cast<double>(li);
+        seg[q] = SB[i] - d.SB0;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kPlanUnroll; ++q) {
+    const PlanCtx d = ctx(q);
+    if (flo[q] < fhi[q]) claim_units(d, flo[q], fhi[q], seg[q], cl[q] - d.C0, lane_seg, lane_cum);
+    if (live[q]) A[idx[q]] = wu[q] / d.S;   // a_u of Alg. 1, once per source
+  }
+}
 
 template <bool kOne>
 __device__ __forceinline__ void lane_plan_sources(const WsHeader* hdr) {
   const GraphDesc* desc = hdr->desc;
-  const uint32_t G = kOne ? 1u : hdr->G;
   const uint64_t total_r = hdr->total_r;
-  const gptr<uint64_t> C = to_global(hdr->C);
-  const gptr<uint64_t> SB = to_global(hdr->SB);
-  const gout<double> A = to_global_mut(hdr->A);
-  const gout<uint32_t> lane_seg = to_global_mut(hdr->lane_seg);
-  const gout<uint64_t> lane_cum = to_global_mut(hdr->lane_cum);
-  const PlanCtx c0 = plan_ctx(desc[0]);
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i0 < total_r;
-       i0 += kPlanUnroll * stride) {
-    uint32_t gq[kPlanUnroll];
-    bool live[kPlanUnroll];
-    double wu[kPlanUnroll];
-    uint64_t cl[kPlanUnroll], ch[kPlanUnroll];
+  const PlanArrays pa{total_r, to_global(hdr->C), to_global(hdr->SB), to_global_mut(hdr->A),
+                      to_global_mut(hdr->lane_seg), to_global_mut(hdr->lane_cum)};
+  uint64_t idx[kPlanUnroll];
+  if constexpr (kOne) {
+    const PlanCtx c0 = plan_ctx(desc[0]);
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i0 < total_r;
+         i0 += kPlanUnroll * stride) {
 #pragma unroll
-    for (int q = 0; q < kPlanUnroll; ++q) {
-      const uint64_t i = i0 + q * stride;
-      gq[q] = (G == 1) ? 0u : find_graph(G, i < total_r ? i : 0, [&](uint32_t x) { return desc[x].r_off; });
-      const PlanCtx d = (G == 1) ? c0 : plan_ctx(desc[gq[q]]);
-      const uint64_t r = i - d.r_off;
-      live[q] = (i < total_r) && (r < d.nr);   // r < nr: C[i + 1] is the graph's own
-      wu[q] = live[q] ? to_global(d.w)[d.u_begin + r] : 0.0;
-      cl[q] = live[q] ? C[i] : 0;
-      ch[q] = live[q] ? C[i + 1] : 0;
+      for (int q = 0; q < kPlanUnroll; ++q) idx[q] = i0 + q * stride;
+      plan_sources_step(pa, idx, [&](int) { return c0; });
     }
-    // the unit starts of the one-segment sources (graph-relative segment
-    // NH + r - H), computed before any store: a wait for a load also waits
-    // for the stores issued before it
-    double flo[kPlanUnroll], fhi[kPlanUnroll];
-    uint64_t seg[kPlanUnroll];
+  } else {
+    const uint32_t G = hdr->G;
+    auto roff = [&](uint32_t x) { return desc[x].r_off; };
+    const uint64_t ntiles = (total_r + kPlanTile - 1) / kPlanTile;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+      const uint64_t tb = tile * kPlanTile;
+      const uint64_t te = ((tb + kPlanTile < total_r) ? tb + kPlanTile : total_r) - 1;
+      const uint32_t g0 = uni32(find_graph(G, tb, roff));
+      const uint32_t g1 = uni32(find_graph_in(g0, G - 1, te, roff));
 #pragma unroll
-    for (int q = 0; q < kPlanUnroll; ++q) {
-      flo[q] = 0.0;
-      fhi[q] = 0.0;
-      seg[q] = 0;
-      if (!live[q]) continue;
-      const uint64_t i = i0 + q * stride;
-      const PlanCtx d = (G == 1) ? c0 : plan_ctx(desc[gq[q]]);
-      const uint64_t r = i - d.r_off;
-      if (d.equal_cost_units()) {
-        if (r < d.H) continue;   // claimed segment by segment with the heavy table
-        flo[q] = (r == 0) ? -1.0 : d.unit_at(static_cast<double>(cl[q] - d.C0));
-        fhi[q] = d.unit_at(static_cast<double>(ch[q] - d.C0));
-        seg[q] = d.NH + (r - d.H);
-      } else if (d.L != 0 && d.policy == 1) {
-        // equal source counts: unit li starts at source floor(li nr / L), segment 0
-        // (L <= nr, so a source starts at most one unit); round-robin starts
-        // (policy 2) are set with the groups
-        const uint64_t L = d.L;
-        const uint64_t li = (r * L + d.nr - 1) / d.nr;          // ceil(r L / nr)
-        if (li < L && (li * d.nr) / L == r) {
-          flo[q] = static_cast<double>(li) - 1.0;
-          fhi[q] = static_cast<double>(li);
-          seg[q] = SB[i] - d.SB0;
-        }
+      for (int q = 0; q < kPlanUnroll; ++q) idx[q] = tb + static_cast<uint64_t>(q) * blockDim.x + threadIdx.x;
+      if (g0 == g1) {
+        const PlanCtx dg = plan_ctx(desc[g0]);
+        plan_sources_step(pa, idx, [&](int) { return dg; });
+      } else {
+        uint32_t gq[kPlanUnroll];
+#pragma unroll
+        for (int q = 0; q < kPlanUnroll; ++q) gq[q] = find_graph_in(g0, g1, idx[q] < te ? idx[q] : te, roff);
+        plan_sources_step(pa, idx, [&](int q) { return plan_ctx(desc[gq[q]]); });
       }
-    }
-#pragma unroll
-    for (int q = 0; q < kPlanUnroll; ++q) {
-      const PlanCtx d = (G == 1) ? c0 : plan_ctx(desc[gq[q]]);
-      if (flo[q] < fhi[q]) claim_units(d, flo[q], fhi[q], seg[q], cl[q] - d.C0, lane_seg, lane_cum);
-      if (live[q]) A[i0 + q * stride] = wu[q] / d.S;   // a_u of Alg. 1, once per source
     }
   }
 }
