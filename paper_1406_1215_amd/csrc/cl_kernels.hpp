@@ -77,6 +77,18 @@ __device__ __forceinline__ uint32_t find_graph_in(uint32_t lo, uint32_t hi, uint
   return lo;
 }
 
+// largest g >= from with off(g) <= i, for off(from) <= i: a few steps forward
+// one graph at a time (a tile walk meets a new graph rarely), then a search
+// of the rest (many small graphs)
+template <class F>
+__device__ __forceinline__ uint32_t advance_graph(uint32_t G, uint32_t from, uint64_t i, F off) {
+  for (int step = 0; step < 4; ++step) {
+    if (from + 1 >= G || off(from + 1) > i) return from;
+    ++from;
+  }
+  return find_graph_in(from, G - 1, i, off);
+}
+
 // first v in [lo, hi] with Qrel(v) >= target; Qrel(hi) >= target is assumed
 __device__ __forceinline__ uint64_t q_lower_bound(const uint64_t* Q, uint64_t q_off, uint64_t Qbase,
                                                   uint64_t lo, uint64_t hi, uint64_t target) {
@@ -115,7 +127,7 @@ __device__ __forceinline__ void bin_flush(unsigned long long* lds, int b, uint64
 // slots per graph, the last one of each graph ignored).  With bins != null
 // (single graph), also accumulates the exact sum.  A single graph's fields
 // are read once and its flags ORed once per thread; each thread handles
-// kValUnroll slots per step, their loads issued together.
+// kValUnroll slots of a tile per step, their loads issued together.
 constexpr int kValUnroll = 4;
 constexpr uint64_t kValTile = 256 * kValUnroll;   // slots per tile (several graphs)
 
@@ -190,32 +202,32 @@ __global__ void __launch_bounds__(256) k_validate(GraphDesc* desc, uint32_t G, u
       }
     }
   };
+  // each block walks a run of consecutive tiles of kValTile slots (with the
+  // weights sorted, a thread's items then mostly share an exponent, so its
+  // sum accumulator rarely flushes); with several graphs, a tile inside one
+  // graph reads that graph's fields once, by block-uniform loads, and a tile
+  // across graphs searches only the graphs it spans
   uint64_t idx[kValUnroll];
   ValView dv[kValUnroll];
-  if (G == 1) {
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i0 < total_slots;
-         i0 += kValUnroll * stride) {
+  auto qoff = [&](uint32_t q) { return desc[q].q_off; };
+  const uint64_t ntiles = (total_slots + kValTile - 1) / kValTile;
+  const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;   // consecutive tiles per block
+  const uint64_t t_end = ((blockIdx.x + 1) * per < ntiles) ? (blockIdx.x + 1) * per : ntiles;
+  uint32_t gc = 0;   // graph of the last tile's end (the walk only moves forward)
+  bool first = true;
+  for (uint64_t tile = blockIdx.x * per; tile < t_end; ++tile) {
+    const uint64_t tb = tile * kValTile;
+    const uint64_t te = ((tb + kValTile < total_slots) ? tb + kValTile : total_slots) - 1;
 #pragma unroll
-      for (int r = 0; r < kValUnroll; ++r) {
-        idx[r] = i0 + r * stride;
-        dv[r] = v0;
-      }
-      step(idx, dv);
-    }
-  } else {
-    // several graphs: tiles of kValTile consecutive slots; a tile inside one
-    // graph reads that graph's fields once, by block-uniform loads, and a
-    // tile across graphs searches only the graphs it spans
-    auto qoff = [&](uint32_t q) { return desc[q].q_off; };
-    const uint64_t ntiles = (total_slots + kValTile - 1) / kValTile;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-      const uint64_t tb = tile * kValTile;
-      const uint64_t te = ((tb + kValTile < total_slots) ? tb + kValTile : total_slots) - 1;
-      const uint32_t g0 = uni32(find_graph(G, tb, qoff));
-      const uint32_t g1 = uni32(find_graph_in(g0, G - 1, te, qoff));
+    for (int r = 0; r < kValUnroll; ++r) idx[r] = tb + static_cast<uint64_t>(r) * blockDim.x + threadIdx.x;
+    if (G == 1) {
 #pragma unroll
-      for (int r = 0; r < kValUnroll; ++r) idx[r] = tb + static_cast<uint64_t>(r) * blockDim.x + threadIdx.x;
+      for (int r = 0; r < kValUnroll; ++r) dv[r] = v0;
+    } else {
+      const uint32_t g0 = uni32(first ? find_graph(G, tb, qoff) : advance_graph(G, gc, tb, qoff));
+      const uint32_t g1 = uni32(advance_graph(G, g0, te, qoff));
+      gc = g1;
+      first = false;
       if (g0 == g1) {
         const ValView vg = view(g0);
 #pragma unroll
@@ -224,8 +236,8 @@ __global__ void __launch_bounds__(256) k_validate(GraphDesc* desc, uint32_t G, u
 #pragma unroll
         for (int r = 0; r < kValUnroll; ++r) dv[r] = view(find_graph_in(g0, g1, idx[r] < te ? idx[r] : te, qoff));
       }
-      step(idx, dv);
     }
+    step(idx, dv);
   }
   if (flags0) atomicOr(&desc[0].status, flags0);
   if (want_sum) {
@@ -710,9 +722,9 @@ __global__ void __launch_bounds__(256) k_heavy_table(const WsHeader* hdr) {
 // cost prefixes) issued together before any of them is used.  A single
 // graph has its own instance (kOne) with no per-source descriptor loads,
 // whose waits would also wait for the stores in flight.  Several graphs are
-// walked in tiles of kPlanTile consecutive sources: a tile inside one graph
-// reads that graph's fields once, by block-uniform loads; a tile across
-// graphs searches only the graphs it spans.
+// walked in tiles of kPlanTile consecutive sources, a run of consecutive
+// tiles per block: a tile inside one graph reads that graph's fields once, by
+// block-uniform loads; a tile across graphs searches only the graphs it spans.
 constexpr int kPlanUnroll = 4;
 constexpr uint64_t kPlanTile = 256 * kPlanUnroll;
 
@@ -808,11 +820,17 @@ __device__ __forceinline__ void lane_plan_sources(const WsHeader* hdr) {
     const uint32_t G = hdr->G;
     auto roff = [&](uint32_t x) { return desc[x].r_off; };
     const uint64_t ntiles = (total_r + kPlanTile - 1) / kPlanTile;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;   // consecutive tiles per block
+    const uint64_t t_end = ((blockIdx.x + 1) * per < ntiles) ? (blockIdx.x + 1) * per : ntiles;
+    uint32_t gc = 0;   // graph of the last tile's end (the walk only moves forward)
+    bool first = true;
+    for (uint64_t tile = blockIdx.x * per; tile < t_end; ++tile) {
       const uint64_t tb = tile * kPlanTile;
       const uint64_t te = ((tb + kPlanTile < total_r) ? tb + kPlanTile : total_r) - 1;
-      const uint32_t g0 = uni32(find_graph(G, tb, roff));
-      const uint32_t g1 = uni32(find_graph_in(g0, G - 1, te, roff));
+      const uint32_t g0 = uni32(first ? find_graph(G, tb, roff) : advance_graph(G, gc, tb, roff));
+      const uint32_t g1 = uni32(advance_graph(G, g0, te, roff));
+      gc = g1;
+      first = false;
 #pragma unroll
       for (int q = 0; q < kPlanUnroll; ++q) idx[q] = tb + static_cast<uint64_t>(q) * blockDim.x + threadIdx.x;
       if (g0 == g1) {
